@@ -1,0 +1,212 @@
+"""FP64 CPU oracle for the multigrid pressure solve (TEST INFRASTRUCTURE ONLY).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  The product library never calls it.  The C source
+(``mg_oracle.c`` + ``mg_ops.inc``) is a plain, unoptimised transcription of the
+method of Sec. 2.3 of the paper (features 1-6, eqs. 10-15); this module only
+marshals numpy arrays into it.
+
+Parity pins for every function live in ``tests/test_oracle_pins.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle_mg.so")
+SOURCES = [os.path.join(HERE, "mg_oracle.c"), os.path.join(HERE, "mg_ops.inc")]
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C99 + OpenMP, no FMA contraction)."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-std=c99", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+           "-D_POSIX_C_SOURCE=200809L", "-o", tmp, SOURCES[0], "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+
+
+class OgOpts(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("n_coarsest", ctypes.c_int),
+                ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int),
+                ("inner_m", ctypes.c_int), ("tol", ctypes.c_double)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        i = ctypes.c_int
+        L.og_plan.argtypes = [i, i, i, i, _I]
+        L.og_plan.restype = i
+        L.og_apply.argtypes = [i, i, i, _D, _D, _D, _D, _D]
+        L.og_residual.argtypes = [i, i, i, _D, _D, _D, _D, _D, _D]
+        L.og_rb_half.argtypes = [i, i, i, _D, _D, _D, _D, _D, i]
+        L.og_restrict.argtypes = [i, i, i, _D, _D]
+        L.og_prolong_add.argtypes = [i, i, i, _D, _D, _D]
+        L.og_coarsen_faces.argtypes = [i, i, i, _D, _D, _D, _D, _D, _D]
+        L.og_cell_weights.argtypes = [i, i, i, _D, _D, _D, _D]
+        L.og_dense_solve.argtypes = [i, i, i, _D, _D, _D, _D, _D]
+        L.og_dense_solve.restype = i
+        L.og_hierarchy_level.argtypes = [i, i, i, _D, _D, _D, i, i, _D, _D, _D, _D]
+        L.og_hierarchy_level.restype = i
+        L.og_solve.argtypes = [i, i, i, _D, _D, _D, _D, _D, ctypes.POINTER(OgOpts), _D, _I, _D, _D]
+        L.og_solve.restype = i
+        L.og_num_threads.restype = i
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def _c(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def dims_of(b):
+    nz, ny, nx = b.shape
+    return nx, ny, nz
+
+
+def plan(n, n_coarsest):
+    nx, ny, nz = n
+    out = (ctypes.c_int * 72)()
+    L = lib().og_plan(nx, ny, nz, n_coarsest, out)
+    return [tuple(out[3 * l:3 * l + 3]) for l in range(L)]
+
+
+def apply(bx, by, bz, p):
+    p = _c(p)
+    nx, ny, nz = dims_of(p)
+    out = np.empty_like(p)
+    bx, by, bz = _c(bx), _c(by), _c(bz)
+    lib().og_apply(nx, ny, nz, _p(bx), _p(by), _p(bz), _p(p), _p(out))
+    return out
+
+
+def residual(bx, by, bz, p, b):
+    p, b = _c(p), _c(b)
+    nx, ny, nz = dims_of(p)
+    r = np.empty_like(p)
+    bx, by, bz = _c(bx), _c(by), _c(bz)
+    lib().og_residual(nx, ny, nz, _p(bx), _p(by), _p(bz), _p(p), _p(b), _p(r))
+    return r
+
+
+def rb_half(bx, by, bz, p, b, colour):
+    p = _c(p).copy()
+    b = _c(b)
+    nx, ny, nz = dims_of(p)
+    bx, by, bz = _c(bx), _c(by), _c(bz)
+    lib().og_rb_half(nx, ny, nz, _p(bx), _p(by), _p(bz), _p(p), _p(b), int(colour))
+    return p
+
+
+def restrict(r):
+    r = _c(r)
+    nx, ny, nz = dims_of(r)
+    rc = np.empty((nz // 2, ny // 2, nx // 2))
+    lib().og_restrict(nx, ny, nz, _p(r), _p(rc))
+    return rc
+
+
+def prolong_add(a, ec, ef):
+    a, ec = _c(a), _c(ec)
+    ef = _c(ef).copy()
+    cnx, cny, cnz = dims_of(ec)
+    assert ef.shape == (2 * cnz, 2 * cny, 2 * cnx)
+    lib().og_prolong_add(cnx, cny, cnz, _p(a), _p(ec), _p(ef))
+    return ef
+
+
+def coarsen_faces(bx, by, bz):
+    bx, by, bz = _c(bx), _c(by), _c(bz)
+    nz, ny, nxp = bx.shape
+    nx = nxp - 1
+    cx, cy, cz = nx // 2, ny // 2, nz // 2
+    cbx = np.empty((cz, cy, cx + 1))
+    cby = np.empty((cz, cy + 1, cx))
+    cbz = np.empty((cz + 1, cy, cx))
+    lib().og_coarsen_faces(nx, ny, nz, _p(bx), _p(by), _p(bz), _p(cbx), _p(cby), _p(cbz))
+    return cbx, cby, cbz
+
+
+def cell_weights(bx, by, bz):
+    bx, by, bz = _c(bx), _c(by), _c(bz)
+    nz, ny, nxp = bx.shape
+    a = np.empty((nz, ny, nxp - 1))
+    lib().og_cell_weights(nxp - 1, ny, nz, _p(bx), _p(by), _p(bz), _p(a))
+    return a
+
+
+def dense_solve(bx, by, bz, rhs):
+    rhs = _c(rhs)
+    nx, ny, nz = dims_of(rhs)
+    e = np.empty_like(rhs)
+    bx, by, bz = _c(bx), _c(by), _c(bz)
+    rc = lib().og_dense_solve(nx, ny, nz, _p(bx), _p(by), _p(bz), _p(rhs), _p(e))
+    if rc != 0:
+        raise ValueError("coarse operator is not positive definite")
+    return e
+
+
+def hierarchy_level(bx, by, bz, n_coarsest, level):
+    """Faces and cell weights of hierarchy level ``level``."""
+    bx, by, bz = _c(bx), _c(by), _c(bz)
+    nz, ny, nxp = bx.shape
+    n = (nxp - 1, ny, nz)
+    dims = plan(n, n_coarsest)
+    cx, cy, cz = dims[level]
+    obx = np.empty((cz, cy, cx + 1))
+    oby = np.empty((cz, cy + 1, cx))
+    obz = np.empty((cz + 1, cy, cx))
+    oa = np.empty((cz, cy, cx))
+    rc = lib().og_hierarchy_level(n[0], n[1], n[2], _p(bx), _p(by), _p(bz), n_coarsest, level,
+                                  _p(obx), _p(oby), _p(obz), _p(oa))
+    if rc != 0:
+        raise ValueError("bad level")
+    return obx, oby, obz, oa
+
+
+STATUS = {0: "converged", 1: "not_converged", 2: "diverged", -1: "invalid"}
+
+
+def solve(bx, by, bz, b, p0=None, nu1=2, nu2=2, n_coarsest=4, max_cycles=100, tol=1e-10,
+          precision="fp64", inner_m=1):
+    """Run the oracle solve.  Returns dict(p, history, cycles, status, gamma, mean_b)."""
+    b = _c(b)
+    nx, ny, nz = dims_of(b)
+    p = np.zeros_like(b) if p0 is None else _c(p0).copy()
+    o = OgOpts(nu1, nu2, n_coarsest, max_cycles, {"fp64": 0, "fp32_refined": 1}[precision],
+               inner_m, tol)
+    hist = np.zeros(max_cycles + 1)
+    ncyc = ctypes.c_int(0)
+    mean_b = ctypes.c_double(0)
+    gamma = ctypes.c_double(0)
+    bx, by, bz = _c(bx), _c(by), _c(bz)
+    rc = lib().og_solve(nx, ny, nz, _p(bx), _p(by), _p(bz), _p(b), _p(p), ctypes.byref(o),
+                        _p(hist), ctypes.byref(ncyc), ctypes.byref(mean_b), ctypes.byref(gamma))
+    return dict(p=p, history=hist[:ncyc.value + 1].copy(), cycles=ncyc.value,
+                status=STATUS[rc], gamma=gamma.value, mean_b=mean_b.value)
+
+
+def num_threads() -> int:
+    return lib().og_num_threads()
