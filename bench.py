@@ -1,0 +1,201 @@
+#!/usr/bin/env python
+"""Benchmark of the multigrid pressure solve on one MI355X.
+
+Workload (default): the 512^3 drop-splash field with a Fourier-perturbed film
+(density ratio 1000, divergence right-hand side, seed 2), coarsest grid 8^3,
+V(2,2) cycles.  One step = one solve to relative residual 1e-10 from p = 0 with
+the FP32-refined solver (FP32 V-cycles inside FP64 iterative refinement), the
+hierarchy already resident (setup is timed separately and reported).  The same
+number of plain FP64 multigrid solves is timed for the comparison the metric
+asks for.
+
+Prints ONE JSON line.  value = milliseconds per FP32-refined solve (lower is
+better); extra keys carry the FP64 time, the speed ratio, achieved HBM GB/s per
+V-cycle, cell-updates/s, the roofline of the dominant kernel and the CPU oracle
+baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "time to 1e-10 residual + HBM GB/s per V-cycle; FP32-refined vs FP64 MG"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_solves(S, b, p, steps, warmup, tol):
+    import torch
+    for _ in range(warmup):
+        p.zero_()
+        st = S.solve(b, p, tol=tol)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stats = []
+    e0.record()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p.zero_()
+        stats.append(S.solve(b, p, tol=tol))
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    return e0.elapsed_time(e1) / steps, wall / steps, stats
+
+
+def profiled(build, b, p, tol):
+    """One extra solve of the same workload with the library's profile mode on:
+    every kernel launch bracketed by HIP events on the solve stream."""
+    S, _ = build(profile=True)
+    p.zero_()
+    st = S.solve(b, p, tol=tol)
+    S.close()
+    return st
+
+
+def cpu_baseline(P, n_coarsest, outer_needed, precision):
+    """The oracle, timed on the host: hierarchy setup plus one outer iteration of
+    the same solve, scaled to the number of iterations the GPU needed."""
+    import oracle
+    oracle.lib()
+    t0 = time.perf_counter()
+    r = oracle.solve(P.bx, P.by, P.bz, P.b, n_coarsest=n_coarsest, max_cycles=1, tol=1e-10,
+                     precision=precision)
+    wall = time.perf_counter() - t0
+    setup_s, rest_s = oracle.last_timing()
+    # rest_s = projection + initial residual + 1 iteration (+ residual); scale the
+    # iteration part by the GPU's count
+    est_s = setup_s + rest_s * outer_needed
+    return dict(value=est_s * 1e3, unit="ms", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{precision} oracle on the same {P.n[0]}^3 input: hierarchy setup "
+                       f"({setup_s:.2f} s) + one outer iteration with its residual "
+                       f"({rest_s:.2f} s), scaled to {outer_needed} iterations; "
+                       f"{wall:.1f} s of CPU wall time measured")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--n-coarsest", type=int, default=8)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(independent problems shard across GPUs without communication, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1410_8568_amd import inputs, mg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t = time.perf_counter()
+    P = inputs.config2(args.n)
+    log(f"generated {args.n}^3 drop-splash input in {time.perf_counter() - t:.1f} s")
+    bx, by, bz, b = mg.to_device(P, dev)
+    torch.cuda.synchronize()
+    N = args.n ** 3
+
+    def build(precision, profile=False):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S = mg.Solver(bx, by, bz, precision=precision, n_coarsest=args.n_coarsest, profile=profile)
+        torch.cuda.synchronize()
+        return S, (time.perf_counter() - t0) * 1e3
+
+    p = torch.zeros_like(b)
+    S32, setup32 = build("fp32_refined")
+    log(f"fp32_refined setup {setup32:.1f} ms")
+    ms32, wall32, st32 = timed_solves(S32, b, p, args.steps, args.warmup, args.tol)
+    last32 = st32[-1]
+    p32 = p.clone()
+    log(f"fp32_refined: {ms32:.2f} ms/solve, outer {last32['outer']}, rho {last32['rel_residual']:.2e}")
+    S32.close()
+    prof32 = profiled(lambda profile: build("fp32_refined", profile), b, p, args.tol)
+
+    res = {}
+    if not args.no_fp64:
+        S64, setup64 = build("fp64")
+        ms64, wall64, st64 = timed_solves(S64, b, p, args.steps, args.warmup, args.tol)
+        last64 = st64[-1]
+        log(f"fp64: {ms64:.2f} ms/solve, cycles {last64['cycles']}, rho {last64['rel_residual']:.2e}")
+        p64 = p.clone()
+        S64.close()
+        prof64 = profiled(lambda profile: build("fp64", profile), b, p, args.tol)
+        rel = (torch.linalg.vector_norm(p32 - p64) / torch.linalg.vector_norm(p64)).item()
+        res.update(fp64_ms_per_solve=ms64, fp64_setup_ms=setup64, fp64_cycles=last64["cycles"],
+                   fp64_final_rel_residual=last64["rel_residual"], fp64_gamma=last64["gamma"],
+                   speedup_fp32_refined_vs_fp64=ms64 / ms32,
+                   rel_l2_fp32_refined_vs_fp64=rel)
+        cyc64 = last64["cycles"]
+        bytes64 = sum(prof64["kernel_bytes"].values())
+        res["fp64_gbps_per_vcycle"] = bytes64 / cyc64 / 1e6 / (ms64 / cyc64)
+        res["fp64_cell_updates_per_s"] = N * cyc64 / (ms64 * 1e-3)
+
+    # dominant kernel of the timed (FP32-refined) step, from the profiled solve
+    kms = prof32["kernel_ms"]
+    dom = max((k for k in kms if k != "smooth"), key=lambda k: kms[k])
+    dom_launch = prof32["kernel_launches"][dom]
+    dom_avg_ms = kms[dom] / dom_launch
+    dom_bytes = prof32["kernel_bytes"][dom] / dom_launch
+    achieved = dom_bytes / (dom_avg_ms * 1e-3) / 1e9
+    cyc32 = last32["cycles"]
+    bytes32 = sum(prof32["kernel_bytes"].values())
+
+    out = {
+        "metric": METRIC,
+        "value": ms32,
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32-inner/f64-outer",
+        "data": "synthetic",
+        "config": {"workload": f"drop splash {args.n}^3, Fourier-perturbed film, density ratio 1000, "
+                               f"divergence rhs seed 2, V(2,2), coarsest {args.n_coarsest}^3, tol {args.tol:g}",
+                   "cells": N, "parallelism": "single GPU"},
+        "setup_ms": setup32,
+        "wall_ms_per_step": wall32,
+        "fp32_refined_outer": last32["outer"],
+        "fp32_refined_cycles": cyc32,
+        "final_rel_residual": last32["rel_residual"],
+        "gamma": last32["gamma"],
+        "gbps_per_vcycle": bytes32 / cyc32 / 1e6 / (ms32 / cyc32),
+        "cell_updates_per_s": N * cyc32 / (ms32 * 1e-3),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "avg_launch_ms": dom_avg_ms, "bytes_per_launch": dom_bytes},
+        "kernel_ms_fp32_refined": prof32["kernel_ms"],
+    }
+    out.update(res)
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(P, args.n_coarsest, last32["outer"], "fp32_refined")
+        except Exception as e:  # the baseline is a report, never the product path
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,233 @@
+/*
+ * mg.h - C ABI of the MI355X (gfx950) variable-coefficient multigrid pressure
+ * solver.
+ *
+ * The solver computes the pressure of the projection step of a two-phase
+ * incompressible flow solver: the non-separable Poisson equation
+ *     div( (1/rho) grad p ) = S                                   (paper eq. 9)
+ * discretised with the cell-centred second-order scheme of eq. (10) on a
+ * uniform grid of cubic cells, homogeneous Neumann walls.  In three dimensions
+ * and with the h^2 of eq. (10) folded into the right-hand side b:
+ *     (L p)_c = sum over the 6 faces f of c of  beta_f (p_nb(f) - p_c) = b_c,
+ * beta_f = the face value of alpha = 1/rho (for example the harmonic estimate of
+ * eqs. 11-12 or an arithmetic average; the library takes faces, not cells).
+ *
+ * The result is the unique mean-zero p with L p = b - mean(b) (the Neumann
+ * problem is solvable only for the mean-free part of b).  It is reached with the
+ * modified V-cycle of Sec. 2.3 (features 1-6): red-black Gauss-Seidel smoothing,
+ * residual restriction by linear interpolation, flux-conserving prolongation
+ * (eqs. 13-14), coarse operators rediscretised from averaged faces, an exact
+ * coarsest-grid solve, and convergence reported with the average reduction rate
+ * gamma of eq. (15).  An FP32-refined mode runs the V-cycles in FP32 inside an
+ * FP64 iterative refinement loop.
+ *
+ * ---------------------------------------------------------------------------
+ * Layout (all arrays device memory, C order, i fastest):
+ *   cells   p, b:  [nz][ny][nx]          double
+ *   x-faces bx:    [nz][ny][nx+1]        face i lies between cells i-1 and i
+ *   y-faces by:    [nz][ny+1][nx]        face j lies between cells j-1 and j
+ *   z-faces bz:    [nz+1][ny][nx]        face k lies between cells k-1 and k
+ * Wall faces (i = 0 or nx, j = 0 or ny, k = 0 or nz) are ignored and treated
+ * as 0.  Every interior face coefficient must be finite and > 0.
+ *
+ * Streams are hipStream_t passed as void* (NULL = the default stream).  Every
+ * call returns an mg_status; no C++ exception crosses this boundary.  A handle
+ * is not thread-safe; a server is.
+ * ---------------------------------------------------------------------------
+ */
+#ifndef MG_H_
+#define MG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MG_OK = 0,
+    MG_PENDING = 1,             /* mg_poll: request not finished yet */
+    MG_E_INVALID = -1,          /* bad argument, grid, option or coefficient */
+    MG_E_WORKSPACE = -2,        /* workspace missing, misaligned or too small */
+    MG_E_HIP = -3,              /* a HIP runtime call failed (message in mg_last_error) */
+    MG_E_NOT_CONVERGED = -4,    /* max_cycles reached; p holds the last iterate */
+    MG_E_DIVERGED = -5,         /* residual became NaN or grew by > 1e6 */
+    MG_E_BUDGET = -6,           /* request footprint exceeds the server arena */
+    MG_E_NOT_FOUND = -7         /* unknown ticket */
+} mg_status;
+
+typedef enum { MG_FP64 = 0, MG_FP32_REFINED = 1 } mg_precision;
+typedef enum { MG_BC_NEUMANN = 0 } mg_bc;
+
+typedef struct {
+    int nx, ny, nz; /* cells per direction, each >= 2 */
+} mg_grid;
+
+#define MG_MAX_LEVELS 24
+#define MG_MAX_COARSE_CELLS 512   /* the coarsest grid is solved by a dense inverse */
+#define MG_MAX_HISTORY 256
+
+typedef struct {
+    int precision;   /* mg_precision */
+    int nu1, nu2;    /* pre- and post-smoothing red-black sweeps (default 2, 2) */
+    int n_coarsest;  /* halve every dimension while all are even and the largest
+                        exceeds n_coarsest (default 4); the coarsest grid must have
+                        <= MG_MAX_COARSE_CELLS cells */
+    int inner_m;     /* FP32 V-cycles per FP64 outer iteration (refined mode, default 1) */
+    int max_cycles;  /* V-cycles (FP64) or outer iterations (refined), default 100 */
+    int profile;     /* nonzero: time every kernel launch with HIP events (stats.kernel_*) */
+} mg_options;
+
+/* Kernel classes reported in mg_stats when options.profile is set. */
+enum {
+    MG_K_SMOOTH = 0,      /* red-black Gauss-Seidel sweeps, all levels */
+    MG_K_RESTRICT = 1,    /* residual + restriction, all levels */
+    MG_K_PROLONG = 2,     /* prolongation + correction, all levels */
+    MG_K_COARSE = 3,      /* coarsest dense solve */
+    MG_K_NORM = 4,        /* convergence residual + norm (FP64 mode) */
+    MG_K_REFINE = 5,      /* FP64 refinement residual and update (refined mode) */
+    MG_K_OTHER = 6,       /* projections, reductions, fills */
+    MG_K_SMOOTH_FINE = 7, /* the smoother on the finest level only (subset of MG_K_SMOOTH) */
+    MG_K_COUNT = 8
+};
+
+typedef struct {
+    int status;                       /* mg_status of the solve */
+    int levels;                       /* hierarchy depth */
+    int cycles;                       /* V-cycles run (FP32 cycles in refined mode) */
+    int outer;                        /* outer iterations (refined) or = cycles (FP64) */
+    int nhist;                        /* entries in history */
+    double history[MG_MAX_HISTORY];   /* relative residual ||b_bar - L p|| / ||b_bar||
+                                         before the first cycle and after each cycle
+                                         (FP64) or outer iteration (refined) */
+    double rel_residual;              /* final relative residual */
+    double gamma;                     /* eq. (15): (R_nc / R_0)^(1/nc) */
+    double mean_b;                    /* mean of b removed before solving */
+    double norm_b;                    /* ||b - mean(b)||_2 */
+    double solve_ms;                  /* wall time of mg_solve (stream synchronised) */
+    double kernel_ms[MG_K_COUNT];     /* summed kernel time per class (profile only) */
+    long long kernel_launches[MG_K_COUNT];
+    double kernel_bytes[MG_K_COUNT];  /* algorithmic HBM bytes per class (profile only) */
+} mg_stats;
+
+typedef struct mg_handle mg_handle;
+
+/* Fill *o with the defaults listed above.  Returns MG_E_INVALID if o is NULL. */
+mg_status mg_default_options(mg_options *o);
+
+/*
+ * Bytes of device workspace mg_setup needs for grid g and options o (hierarchy
+ * faces, cell weights, per-level unknowns/right-hand sides, the FP32 copy in
+ * refined mode, the coarsest dense inverse, reduction scratch).  Pure; no device
+ * call.  Errors: MG_E_INVALID for NULL arguments, a dimension < 2, or a coarsest
+ * grid larger than MG_MAX_COARSE_CELLS.
+ */
+mg_status mg_workspace_bytes(const mg_grid *g, const mg_options *o, size_t *bytes);
+
+/*
+ * Build the hierarchy for one coefficient field (setup steps: copy faces with
+ * zero walls, coarsen faces level by level, cell weights for the prolongation,
+ * dense inverse of the coarsest operator, FP32 copies in refined mode).
+ * bx, by, bz: device double arrays in the layout above; read on `stream`, the
+ * caller may reuse them once the call returns.  ws: caller-owned device
+ * workspace of ws_bytes >= mg_workspace_bytes(), 256-byte aligned, which must
+ * outlive the handle; the library owns its contents until mg_destroy.
+ * bc must be MG_BC_NEUMANN.  Blocking: the stream is synchronised before return.
+ * Errors: MG_E_INVALID (NULL pointer, bad bc, a non-finite or non-positive
+ * interior coefficient found by the device check), MG_E_WORKSPACE, MG_E_HIP.
+ */
+mg_status mg_setup(const mg_grid *g, const mg_options *o, const double *bx, const double *by,
+                   const double *bz, int bc, void *ws, size_t ws_bytes, void *stream,
+                   mg_handle **out);
+
+/*
+ * Solve L p = b - mean(b) to relative residual ||b_bar - L p||_2 / ||b_bar||_2 <= tol.
+ * rhs: device double [nz][ny][nx], not modified.  p: device double, in/out;
+ * on entry the initial guess, on return the mean-zero solution (or the last
+ * iterate).  st (optional, host): statistics.  Blocking on return.
+ * A zero b_bar gives p = 0 and MG_OK.
+ * Errors: MG_E_NOT_CONVERGED (p = last iterate, st valid), MG_E_DIVERGED,
+ * MG_E_INVALID (NULL handle/array, tol not finite or < 0), MG_E_HIP.
+ */
+mg_status mg_solve(mg_handle *h, const double *rhs, double *p, double tol, mg_stats *st,
+                   void *stream);
+
+/* Release host-side state.  The workspace belongs to the caller.  NULL is ignored. */
+void mg_destroy(mg_handle *h);
+
+/* Hierarchy inspection (for tests): number of levels and dims of level l. */
+mg_status mg_level_dims(const mg_handle *h, int l, int *nx, int *ny, int *nz);
+
+/*
+ * Copy level l's FP64 faces and cell weights into caller device buffers of the
+ * layout above (a has [nz][ny][nx]); any pointer may be NULL to skip it.
+ * Runs on `stream` and synchronises it.  Errors: MG_E_INVALID, MG_E_HIP.
+ */
+mg_status mg_copy_level(const mg_handle *h, int l, double *bx, double *by, double *bz, double *a,
+                        void *stream);
+
+/* ------------------------------------------------------------------------- */
+/* Continuous-batching solve server                                           */
+/* ------------------------------------------------------------------------- */
+
+typedef struct mg_server mg_server;
+
+typedef struct {
+    mg_options solver;    /* options for every request (precision, sweeps, ...) */
+    int max_slots;        /* concurrent resident problems (default 16) */
+    void *stream;         /* hipStream_t the server launches on (NULL: default stream) */
+} mg_server_options;
+
+typedef struct {
+    mg_grid grid;
+    const double *bx, *by, *bz;   /* device faces, layout above */
+    const double *rhs;            /* device right-hand side */
+    double *p;                    /* device in/out: initial guess, then the solution */
+    double tol;
+} mg_request;
+
+typedef struct {
+    int status;                   /* final mg_status of the request */
+    mg_stats stats;
+    double submit_ms, start_ms, finish_ms;   /* server clock */
+} mg_result;
+
+/*
+ * Create a server that keeps each admitted request's hierarchy resident in
+ * `arena` (caller-owned device memory of arena_bytes, 256-byte aligned; the HBM
+ * budget).  A scheduler thread admits requests in arrival order as soon as their
+ * workspace fits in the free part of the arena and a slot is free, and advances
+ * every resident problem by one outer iteration per scheduling round; finished
+ * problems release their memory at once.  Errors: MG_E_INVALID, MG_E_HIP.
+ */
+mg_status mg_server_create(void *arena, size_t arena_bytes, const mg_server_options *o,
+                           mg_server **out);
+
+/*
+ * Queue one solve.  The request's arrays must stay valid until mg_poll reports a
+ * final status.  Thread-safe.  Errors: MG_E_BUDGET (workspace larger than the
+ * whole arena), MG_E_INVALID.
+ */
+mg_status mg_batch_submit(mg_server *s, const mg_request *r, uint64_t *ticket);
+
+/*
+ * Non-blocking.  Returns MG_PENDING while the request is queued or running, else
+ * its final status with *out filled (stats, timestamps); the ticket is then
+ * forgotten.  Thread-safe.  Errors: MG_E_NOT_FOUND.
+ */
+mg_status mg_poll(mg_server *s, uint64_t ticket, mg_result *out);
+
+/* Stop the scheduler after finishing all queued work, then free host state. */
+void mg_server_destroy(mg_server *s);
+
+/* Static description of a status code. */
+const char *mg_status_string(mg_status s);
+
+/* Message of the last failed call on this thread (empty string if none). */
+const char *mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MG_H_ */

@@ -68,6 +68,7 @@ def lib():
         L.og_solve.argtypes = [i, i, i, _D, _D, _D, _D, _D, ctypes.POINTER(OgOpts), _D, _I, _D, _D]
         L.og_solve.restype = i
         L.og_num_threads.restype = i
+        L.og_last_timing.argtypes = [_D, _D]
         _lib = L
     return _lib
 
@@ -206,6 +207,13 @@ def solve(bx, by, bz, b, p0=None, nu1=2, nu2=2, n_coarsest=4, max_cycles=100, to
                         _p(hist), ctypes.byref(ncyc), ctypes.byref(mean_b), ctypes.byref(gamma))
     return dict(p=p, history=hist[:ncyc.value + 1].copy(), cycles=ncyc.value,
                 status=STATUS[rc], gamma=gamma.value, mean_b=mean_b.value)
+
+
+def last_timing():
+    """(setup seconds, seconds after setup) of the last solve()."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    lib().og_last_timing(ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 def num_threads() -> int:

@@ -449,12 +449,34 @@ typedef struct {
  * Result codes: 0 converged, 1 not converged within max_cycles, 2 diverged
  * (NaN or growth), -1 invalid input/singular coarse operator.
  */
+static double last_setup_s = 0, last_cycles_s = 0;
+
+/* Wall time of the last og_solve: hierarchy setup, and everything after it. */
+void og_last_timing(double *setup_s, double *cycles_s)
+{
+    *setup_s = last_setup_s;
+    *cycles_s = last_cycles_s;
+}
+
+static double wall(void)
+{
+#ifdef _OPENMP
+    return omp_get_wtime();
+#else
+    return 0.0;
+#endif
+}
+
 int og_solve(int nx, int ny, int nz, const double *bx, const double *by, const double *bz,
              const double *b, double *p, const og_opts *o, double *hist, int *ncycles,
              double *mean_b_out, double *gamma_out)
 {
     hier_t H;
+    double t0 = wall();
     int rc = hier_build(&H, nx, ny, nz, bx, by, bz, o->n_coarsest, o->precision == 1);
+    double t1 = wall();
+    last_setup_s = t1 - t0;
+    last_cycles_s = 0;
     if (rc != 0) {
         hier_free(&H);
         return -1;
@@ -520,6 +542,7 @@ int og_solve(int nx, int ny, int nz, const double *bx, const double *by, const d
         }
     }
     *ncycles = cyc;
+    last_cycles_s = wall() - t1;
     /* average reduction rate, eq. (15) */
     if (gamma_out) *gamma_out = cyc > 0 ? pow(rho / rho0, 1.0 / cyc) : 0.0;
     free(bbar);

@@ -1,0 +1,108 @@
+// Host-side runtime of the multigrid solver: workspace planning, hierarchy
+// setup, V-cycle driver, FP64 iterative refinement.  Shared by the C ABI
+// (mg_core.hip) and the solve server (mg_server.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "../../include/mg.h"
+
+
+namespace mgrt {
+
+void set_error(const std::string& msg);
+
+struct LevelDims {
+    int nx, ny, nz;
+    size_t ncell() const { return (size_t)nx * ny * nz; }
+    size_t nfx() const { return (size_t)(nx + 1) * ny * nz; }
+    size_t nfy() const { return (size_t)nx * (ny + 1) * nz; }
+    size_t nfz() const { return (size_t)nx * ny * (nz + 1); }
+    size_t nfaces() const { return nfx() + nfy() + nfz(); }
+};
+
+// Offsets (bytes from the workspace base) of every device array.
+struct Layout {
+    int nlev = 0;
+    LevelDims d[MG_MAX_LEVELS];
+    size_t bx[MG_MAX_LEVELS], by[MG_MAX_LEVELS], bz[MG_MAX_LEVELS], a[MG_MAX_LEVELS];
+    size_t e[MG_MAX_LEVELS], rhs[MG_MAX_LEVELS];                  // FP64 levels >= 1 (FP64 mode)
+    size_t fbx[MG_MAX_LEVELS], fby[MG_MAX_LEVELS], fbz[MG_MAX_LEVELS], fa[MG_MAX_LEVELS];
+    size_t fe[MG_MAX_LEVELS], frhs[MG_MAX_LEVELS];                // FP32 levels (refined mode)
+    size_t bbar = 0, binv = 0, scal = 0, part = 0, flag = 0;
+    int ncoarse = 0;
+    int max_blocks = 0;
+    size_t total = 0;
+};
+
+// Validates the grid/options and fills the layout.  Returns MG_OK or MG_E_INVALID.
+mg_status plan(const mg_grid* g, const mg_options* o, Layout* L);
+
+dim3 col_grid(int nx, int ny, int nz);
+
+}  // namespace mgrt
+
+struct mg_handle {
+    mg_grid g;
+    mg_options o;
+    mgrt::Layout L;
+    char* ws = nullptr;
+    // typed device pointers
+    double *bx[MG_MAX_LEVELS], *by[MG_MAX_LEVELS], *bz[MG_MAX_LEVELS], *a[MG_MAX_LEVELS];
+    double *e[MG_MAX_LEVELS], *rhs[MG_MAX_LEVELS];
+    float *fbx[MG_MAX_LEVELS], *fby[MG_MAX_LEVELS], *fbz[MG_MAX_LEVELS], *fa[MG_MAX_LEVELS];
+    float *fe[MG_MAX_LEVELS], *frhs[MG_MAX_LEVELS];
+    double* bbar = nullptr;
+    double* binv = nullptr;
+    double* scal = nullptr;
+    double* part = nullptr;
+    int* flag = nullptr;
+    hipStream_t stream = nullptr;
+    double* host = nullptr;  // pinned host copy of device scalars
+    // profiling
+    struct Rec {
+        int cls;
+        double bytes;
+    };
+    std::vector<hipEvent_t> ev;
+    std::vector<Rec> recs;
+    double kernel_ms[MG_K_COUNT];
+    long long kernel_launches[MG_K_COUNT];
+    double kernel_bytes[MG_K_COUNT];
+};
+
+namespace mgrt {
+// Bracket a kernel launch with profiling events when enabled.
+struct Prof {
+    mg_handle* h;
+    int cls;
+    double bytes;
+    size_t idx;
+    Prof(mg_handle* h_, int cls_, double bytes_);
+    ~Prof();
+};
+
+mg_status setup_impl(mg_handle* h, const double* bx, const double* by, const double* bz);
+mg_status solve_impl(mg_handle* h, const double* rhs, double* p, double tol, mg_stats* st);
+
+// Solve as a state machine, so that a scheduler can interleave many problems.
+struct SolveState {
+    mg_handle* h = nullptr;
+    const double* rhs = nullptr;
+    double* p = nullptr;
+    double tol = 0;
+    mg_stats st;
+    double norm_b = 0, rho0 = 0, rho = 0, scale = 1;
+    int it = 0;
+    int status = MG_OK;
+    std::chrono::steady_clock::time_point t0;
+};
+mg_status solve_begin(SolveState& S);             // blocking: projection + initial residual
+mg_status solve_launch_iteration(SolveState& S);  // asynchronous: one (outer) iteration
+void solve_after_sync(SolveState& S);             // after h->stream is synchronised
+bool solve_running(const SolveState& S);
+void solve_end(SolveState& S, mg_stats* st);
+}  // namespace mgrt

@@ -1,0 +1,669 @@
+// Host runtime and C ABI of the multigrid pressure solver (gfx950).
+//
+// Setup (per coefficient field): copy faces with zero walls, coarsen faces
+// level by level, cell weights for the flux-weighted prolongation, dense inverse
+// of the coarsest operator, FP32 copies in refined mode.
+// Solve: project b onto the range of L, then V-cycles (FP64 mode) or FP32
+// V-cycles inside FP64 iterative refinement, with the relative residual, gamma
+// (eq. 15) and the mean-zero projection of p after every cycle.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "mg_core.h"
+#include "mg_kernels.h"
+
+using namespace mgk;
+
+namespace mgrt {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                     \
+            return MG_E_HIP;                                                                  \
+        }                                                                                     \
+    } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+dim3 col_grid(int nx, int ny, int nz) {
+    int gx = (nx + BX - 1) / BX, gy = (ny + BY - 1) / BY;
+    int gz = std::max(1, std::min(nz, 4096 / std::max(1, gx * gy)));
+    return dim3(gx, gy, gz);
+}
+
+static int col_blocks(int nx, int ny, int nz) {
+    dim3 g = col_grid(nx, ny, nz);
+    return (int)(g.x * g.y * g.z);
+}
+
+mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
+    if (!g || !o || !L) {
+        set_error("null argument");
+        return MG_E_INVALID;
+    }
+    if (g->nx < 2 || g->ny < 2 || g->nz < 2) {
+        set_error("every grid dimension must be >= 2");
+        return MG_E_INVALID;
+    }
+    if ((double)g->nx * g->ny * g->nz > 4.0e9) {
+        set_error("grid too large");
+        return MG_E_INVALID;
+    }
+    if (o->precision != MG_FP64 && o->precision != MG_FP32_REFINED) {
+        set_error("unknown precision");
+        return MG_E_INVALID;
+    }
+    if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 16 || o->nu2 > 16 || o->n_coarsest < 1 || o->inner_m < 1 ||
+        o->inner_m > 16 || o->max_cycles < 1 || o->max_cycles > MG_MAX_HISTORY - 1) {
+        set_error("option out of range");
+        return MG_E_INVALID;
+    }
+    *L = Layout();
+    int d[3] = {g->nx, g->ny, g->nz};
+    for (;;) {
+        LevelDims& ld = L->d[L->nlev];
+        ld.nx = d[0];
+        ld.ny = d[1];
+        ld.nz = d[2];
+        L->nlev++;
+        if (L->nlev == MG_MAX_LEVELS) break;
+        int mx = std::max(d[0], std::max(d[1], d[2]));
+        if ((d[0] & 1) || (d[1] & 1) || (d[2] & 1) || mx <= o->n_coarsest) break;
+        d[0] /= 2;
+        d[1] /= 2;
+        d[2] /= 2;
+    }
+    const LevelDims& c = L->d[L->nlev - 1];
+    if (c.ncell() > MG_MAX_COARSE_CELLS) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "coarsest grid %dx%dx%d has more than %d cells", c.nx, c.ny, c.nz,
+                 MG_MAX_COARSE_CELLS);
+        set_error(buf);
+        return MG_E_INVALID;
+    }
+    L->ncoarse = (int)c.ncell();
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = off;
+        off += align256(bytes);
+        return r;
+    };
+    const bool f32 = o->precision == MG_FP32_REFINED;
+    for (int l = 0; l < L->nlev; l++) {
+        const LevelDims& ld = L->d[l];
+        L->bx[l] = take(ld.nfx() * 8);
+        L->by[l] = take(ld.nfy() * 8);
+        L->bz[l] = take(ld.nfz() * 8);
+        L->a[l] = take(ld.ncell() * 8);
+        if (l > 0 && !f32) {
+            L->e[l] = take(ld.ncell() * 8);
+            L->rhs[l] = take(ld.ncell() * 8);
+        }
+        if (f32) {
+            L->fbx[l] = take(ld.nfx() * 4);
+            L->fby[l] = take(ld.nfy() * 4);
+            L->fbz[l] = take(ld.nfz() * 4);
+            L->fa[l] = take(ld.ncell() * 4);
+            L->fe[l] = take(ld.ncell() * 4);
+            L->frhs[l] = take(ld.ncell() * 4);
+        }
+    }
+    L->bbar = take(L->d[0].ncell() * 8);
+    L->binv = take((size_t)L->ncoarse * L->ncoarse * 8);
+    L->scal = take(64 * 8);
+    int mb = 0;
+    for (int l = 0; l < L->nlev; l++) mb = std::max(mb, col_blocks(L->d[l].nx, L->d[l].ny, L->d[l].nz));
+    L->max_blocks = mb;
+    L->part = take((size_t)2 * mb * 8);
+    L->flag = take(64);
+    L->total = off;
+    return MG_OK;
+}
+
+static dim3 lin_grid(size_t n) {
+    size_t b = (n + 255) / 256;
+    return dim3((unsigned)std::max<size_t>(1, std::min<size_t>(b, 16384)));
+}
+
+// ------------------------------------------------------------------ profiling
+
+Prof::Prof(mg_handle* h_, int cls_, double bytes_) : h(h_), cls(cls_), bytes(bytes_), idx(0) {
+    if (!h->o.profile) return;
+    idx = h->recs.size();
+    while (h->ev.size() < 2 * (idx + 1)) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        h->ev.push_back(e);
+    }
+    h->recs.push_back({cls, bytes});
+    (void)hipEventRecord(h->ev[2 * idx], h->stream);
+}
+
+Prof::~Prof() {
+    if (!h->o.profile || h->ev.size() < 2 * (idx + 1)) return;
+    (void)hipEventRecord(h->ev[2 * idx + 1], h->stream);
+}
+
+static void prof_reset(mg_handle* h) {
+    h->recs.clear();
+    for (int c = 0; c < MG_K_COUNT; c++) {
+        h->kernel_ms[c] = 0;
+        h->kernel_launches[c] = 0;
+        h->kernel_bytes[c] = 0;
+    }
+}
+
+static void prof_collect(mg_handle* h) {
+    if (!h->o.profile) return;
+    for (size_t i = 0; i < h->recs.size(); i++) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) != hipSuccess) continue;
+        int c = h->recs[i].cls;
+        h->kernel_ms[c] += ms;
+        h->kernel_launches[c] += 1;
+        h->kernel_bytes[c] += h->recs[i].bytes;
+    }
+    h->recs.clear();
+}
+
+// ------------------------------------------------------------------ setup
+
+static void bind(mg_handle* h) {
+    const Layout& L = h->L;
+    char* w = h->ws;
+    const bool f32 = h->o.precision == MG_FP32_REFINED;
+    for (int l = 0; l < L.nlev; l++) {
+        h->bx[l] = (double*)(w + L.bx[l]);
+        h->by[l] = (double*)(w + L.by[l]);
+        h->bz[l] = (double*)(w + L.bz[l]);
+        h->a[l] = (double*)(w + L.a[l]);
+        h->e[l] = (l > 0 && !f32) ? (double*)(w + L.e[l]) : nullptr;
+        h->rhs[l] = (l > 0 && !f32) ? (double*)(w + L.rhs[l]) : nullptr;
+        if (f32) {
+            h->fbx[l] = (float*)(w + L.fbx[l]);
+            h->fby[l] = (float*)(w + L.fby[l]);
+            h->fbz[l] = (float*)(w + L.fbz[l]);
+            h->fa[l] = (float*)(w + L.fa[l]);
+            h->fe[l] = (float*)(w + L.fe[l]);
+            h->frhs[l] = (float*)(w + L.frhs[l]);
+        } else {
+            h->fbx[l] = h->fby[l] = h->fbz[l] = h->fa[l] = h->fe[l] = h->frhs[l] = nullptr;
+        }
+    }
+    h->bbar = (double*)(w + L.bbar);
+    h->binv = (double*)(w + L.binv);
+    h->scal = (double*)(w + L.scal);
+    h->part = (double*)(w + L.part);
+    h->flag = (int*)(w + L.flag);
+}
+
+mg_status setup_impl(mg_handle* h, const double* bx, const double* by, const double* bz) {
+    bind(h);
+    const Layout& L = h->L;
+    hipStream_t s = h->stream;
+    HIPCHK(hipMemsetAsync(h->flag, 0, 64, s));
+    const LevelDims& d0 = L.d[0];
+    k_copy_faces<<<lin_grid(d0.nfx()), 256, 0, s>>>(bx, h->bx[0], d0.nx + 1, d0.ny, d0.nz, 0, h->flag);
+    k_copy_faces<<<lin_grid(d0.nfy()), 256, 0, s>>>(by, h->by[0], d0.nx, d0.ny + 1, d0.nz, 1, h->flag);
+    k_copy_faces<<<lin_grid(d0.nfz()), 256, 0, s>>>(bz, h->bz[0], d0.nx, d0.ny, d0.nz + 1, 2, h->flag);
+    HIPCHK(hipGetLastError());
+    for (int l = 0; l < L.nlev; l++) {
+        const LevelDims& d = L.d[l];
+        if (l > 0) {
+            const LevelDims& f = L.d[l - 1];
+            k_coarsen_x<<<lin_grid(d.nfx()), 256, 0, s>>>(h->bx[l - 1], h->bx[l], f.nx, f.ny, d.nx, d.ny, d.nz);
+            k_coarsen_y<<<lin_grid(d.nfy()), 256, 0, s>>>(h->by[l - 1], h->by[l], f.nx, f.ny, d.nx, d.ny, d.nz);
+            k_coarsen_z<<<lin_grid(d.nfz()), 256, 0, s>>>(h->bz[l - 1], h->bz[l], f.nx, f.ny, d.nx, d.ny, d.nz);
+        }
+        k_cell_weights<<<lin_grid(d.ncell()), 256, 0, s>>>(h->bx[l], h->by[l], h->bz[l], h->a[l], d.nx, d.ny,
+                                                           d.nz);
+    }
+    HIPCHK(hipGetLastError());
+    const LevelDims& c = L.d[L.nlev - 1];
+    k_coarse_invert<<<1, FIN_THREADS, 0, s>>>(h->bx[L.nlev - 1], h->by[L.nlev - 1], h->bz[L.nlev - 1], c.nx,
+                                              c.ny, c.nz, h->binv, h->flag + 1);
+    HIPCHK(hipGetLastError());
+    if (h->o.precision == MG_FP32_REFINED) {
+        for (int l = 0; l < L.nlev; l++) {
+            const LevelDims& d = L.d[l];
+            k_cast_d2f<<<lin_grid(d.nfx()), 256, 0, s>>>(h->bx[l], h->fbx[l], d.nfx());
+            k_cast_d2f<<<lin_grid(d.nfy()), 256, 0, s>>>(h->by[l], h->fby[l], d.nfy());
+            k_cast_d2f<<<lin_grid(d.nfz()), 256, 0, s>>>(h->bz[l], h->fbz[l], d.nfz());
+            k_cast_d2f<<<lin_grid(d.ncell()), 256, 0, s>>>(h->a[l], h->fa[l], d.ncell());
+        }
+        HIPCHK(hipGetLastError());
+    }
+    int flags[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(flags, h->flag, sizeof flags, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (flags[0]) {
+        set_error(std::to_string(flags[0]) + " interior face coefficient(s) not finite and > 0");
+        return MG_E_INVALID;
+    }
+    if (flags[1]) {
+        set_error("coarsest operator not positive definite (disconnected grid?)");
+        return MG_E_INVALID;
+    }
+    return MG_OK;
+}
+
+// ------------------------------------------------------------------ solve
+
+template <class T>
+struct Hier {
+    int nlev;
+    const LevelDims* d;
+    Lvl<T> L[MG_MAX_LEVELS];
+    T* e[MG_MAX_LEVELS];
+    T* rhs[MG_MAX_LEVELS];
+    const T* a[MG_MAX_LEVELS];
+};
+
+template <class T>
+static double nbytes_sweep_half(const LevelDims& d) {
+    return 0.5 * ((3.0 * d.ncell() + d.nfaces()) * sizeof(T));
+}
+
+template <class T>
+static void vcycle(mg_handle* h, Hier<T>& H, int l) {
+    hipStream_t s = h->stream;
+    const LevelDims& d = H.d[l];
+    if (l == H.nlev - 1) {
+        Prof pf(h, MG_K_COARSE, (double)h->L.ncoarse * h->L.ncoarse * 8 + 2.0 * d.ncell() * sizeof(T));
+        k_coarse_solve<T><<<1, 512, 0, s>>>(h->binv, h->L.ncoarse, H.rhs[l], H.e[l]);
+        return;
+    }
+    const dim3 g = col_grid(d.nx, d.ny, d.nz), blk(BX, BY);
+    const double hb = nbytes_sweep_half<T>(d);
+    const int cls_s = MG_K_SMOOTH;
+    for (int it = 0; it < h->o.nu1; it++) {
+        for (int colour = 0; colour < 2; colour++) {
+            Prof pf(h, l == 0 ? MG_K_SMOOTH_FINE : cls_s, hb);
+            k_rb_half<T><<<g, blk, 0, s>>>(H.L[l], H.e[l], H.rhs[l], colour);
+        }
+    }
+    const LevelDims& c = H.d[l + 1];
+    {
+        Prof pf(h, MG_K_RESTRICT, ((2.0 * d.ncell() + d.nfaces()) + c.ncell()) * sizeof(T));
+        k_residual_restrict<T><<<col_grid(c.nx, c.ny, c.nz), blk, 0, s>>>(H.L[l], H.e[l], H.rhs[l], H.rhs[l + 1]);
+    }
+    {
+        Prof pf(h, MG_K_OTHER, (double)c.ncell() * sizeof(T));
+        k_fill<T><<<lin_grid(c.ncell()), 256, 0, s>>>(H.e[l + 1], c.ncell(), T(0));
+    }
+    vcycle(h, H, l + 1);
+    {
+        Prof pf(h, MG_K_PROLONG, (2.0 * d.ncell() + 2.0 * c.ncell()) * sizeof(T));
+        k_prolong_add<T><<<g, blk, 0, s>>>(H.e[l + 1], H.a[l + 1], c.nx, c.ny, c.nz, H.e[l]);
+    }
+    for (int it = 0; it < h->o.nu2; it++) {
+        for (int colour = 1; colour >= 0; colour--) {
+            Prof pf(h, l == 0 ? MG_K_SMOOTH_FINE : cls_s, hb);
+            k_rb_half<T><<<g, blk, 0, s>>>(H.L[l], H.e[l], H.rhs[l], colour);
+        }
+    }
+}
+
+static double pow2_near(double v) {
+    if (!(v > 0) || !std::isfinite(v)) return 1.0;
+    return std::ldexp(1.0, (int)std::floor(std::log2(v)));
+}
+
+// Run partial-sum kernel output through k_finish2 into scal[slot], scal[slot+1].
+static void finish(mg_handle* h, int nblk, int slot) {
+    Prof pf(h, MG_K_OTHER, 16.0 * nblk);
+    k_finish2<<<1, FIN_THREADS, 0, h->stream>>>(h->part, nblk, h->scal + slot);
+}
+
+static void build_hier(mg_handle* h, double* p, Hier<double>& H64, Hier<float>& H32) {
+    const Layout& L = h->L;
+    H64.nlev = H32.nlev = L.nlev;
+    H64.d = H32.d = L.d;
+    for (int l = 0; l < L.nlev; l++) {
+        const LevelDims& d = L.d[l];
+        H64.L[l] = Lvl<double>{d.nx, d.ny, d.nz, h->bx[l], h->by[l], h->bz[l]};
+        H64.e[l] = l == 0 ? p : h->e[l];
+        H64.rhs[l] = l == 0 ? h->bbar : h->rhs[l];
+        H64.a[l] = h->a[l];
+        if (h->o.precision == MG_FP32_REFINED) {
+            H32.L[l] = Lvl<float>{d.nx, d.ny, d.nz, h->fbx[l], h->fby[l], h->fbz[l]};
+            H32.e[l] = h->fe[l];
+            H32.rhs[l] = h->frhs[l];
+            H32.a[l] = h->fa[l];
+        }
+    }
+}
+
+// Step 1 (blocking): project b, initial residual, history[0].
+mg_status solve_begin(SolveState& S) {
+    mg_handle* h = S.h;
+    S.t0 = std::chrono::steady_clock::now();
+    prof_reset(h);
+    memset(&S.st, 0, sizeof S.st);
+    S.st.levels = h->L.nlev;
+    S.it = 0;
+    const LevelDims& d0 = h->L.d[0];
+    const double N = (double)d0.ncell();
+    hipStream_t s = h->stream;
+    const dim3 g0 = col_grid(d0.nx, d0.ny, d0.nz), blk(BX, BY);
+    const int nb0 = (int)(g0.x * g0.y * g0.z);
+    const bool f32 = h->o.precision == MG_FP32_REFINED;
+    Lvl<double> L64{d0.nx, d0.ny, d0.nz, h->bx[0], h->by[0], h->bz[0]};
+    {
+        Prof pf(h, MG_K_OTHER, 8.0 * N);
+        k_sum_sq<double><<<g0, blk, 0, s>>>(S.rhs, d0.nx, d0.ny, d0.nz, h->part);
+    }
+    finish(h, nb0, 0);
+    {
+        Prof pf(h, MG_K_OTHER, 16.0 * N);
+        k_project<<<g0, blk, 0, s>>>(S.rhs, h->bbar, h->scal, d0.nx, d0.ny, d0.nz, h->part);
+    }
+    finish(h, nb0, 2);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->host, h->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    S.st.mean_b = h->host[0] / N;
+    S.norm_b = std::sqrt(h->host[3]);
+    S.st.norm_b = S.norm_b;
+    if (S.norm_b == 0.0) {
+        k_fill<double><<<lin_grid(d0.ncell()), 256, 0, s>>>(S.p, d0.ncell(), 0.0);
+        HIPCHK(hipStreamSynchronize(s));
+        S.st.nhist = 1;
+        S.st.history[0] = 0.0;
+        S.rho0 = S.rho = 0.0;
+        S.status = MG_OK;
+        return MG_OK;
+    }
+    const double resid_bytes = (2.0 * N + d0.nfaces()) * 8.0;
+    S.scale = pow2_near(S.norm_b / std::sqrt(N));
+    if (f32) {
+        Prof pf(h, MG_K_REFINE, resid_bytes + 4.0 * N);
+        k_refine_residual<<<g0, blk, 0, s>>>(L64, S.p, h->bbar, 1.0 / S.scale, h->frhs[0], h->part);
+    } else {
+        Prof pf(h, MG_K_NORM, resid_bytes);
+        k_resid_norm<double><<<g0, blk, 0, s>>>(L64, S.p, h->bbar, h->part);
+    }
+    finish(h, nb0, 4);
+    {
+        Prof pf(h, MG_K_OTHER, 16.0 * N);
+        k_sub_mean<double><<<g0, blk, 0, s>>>(S.p, h->scal + 5, d0.nx, d0.ny, d0.nz);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->host, h->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    S.rho0 = S.rho = std::sqrt(h->host[0]) / S.norm_b;
+    S.st.history[0] = S.rho0;
+    S.st.nhist = 1;
+    S.status = S.rho0 <= S.tol ? MG_OK : MG_E_NOT_CONVERGED;
+    if (S.status == MG_E_NOT_CONVERGED && S.it >= h->o.max_cycles) S.status = MG_E_NOT_CONVERGED;
+    return MG_OK;
+}
+
+// Step 2 (asynchronous): one V-cycle (FP64) or one outer refinement iteration,
+// the new residual norm, the mean-zero projection of p, and the copy of the two
+// scalars to h->host.  The caller synchronises h->stream before solve_after_sync.
+mg_status solve_launch_iteration(SolveState& S) {
+    mg_handle* h = S.h;
+    const LevelDims& d0 = h->L.d[0];
+    const double N = (double)d0.ncell();
+    hipStream_t s = h->stream;
+    const dim3 g0 = col_grid(d0.nx, d0.ny, d0.nz), blk(BX, BY);
+    const int nb0 = (int)(g0.x * g0.y * g0.z);
+    const bool f32 = h->o.precision == MG_FP32_REFINED;
+    const double resid_bytes = (2.0 * N + d0.nfaces()) * 8.0;
+    Lvl<double> L64{d0.nx, d0.ny, d0.nz, h->bx[0], h->by[0], h->bz[0]};
+    Hier<double> H64;
+    Hier<float> H32;
+    build_hier(h, S.p, H64, H32);
+    if (!f32) {
+        vcycle(h, H64, 0);
+        S.st.cycles++;
+        Prof pf(h, MG_K_NORM, resid_bytes);
+        k_resid_norm<double><<<g0, blk, 0, s>>>(L64, S.p, h->bbar, h->part);
+    } else {
+        {
+            Prof pf(h, MG_K_OTHER, 4.0 * N);
+            k_fill<float><<<lin_grid(d0.ncell()), 256, 0, s>>>(h->fe[0], d0.ncell(), 0.0f);
+        }
+        for (int m = 0; m < h->o.inner_m; m++) {
+            vcycle(h, H32, 0);
+            S.st.cycles++;
+        }
+        {
+            Prof pf(h, MG_K_REFINE, 20.0 * N);
+            k_refine_update<<<g0, blk, 0, s>>>(S.p, h->fe[0], S.scale, d0.nx, d0.ny, d0.nz, h->part);
+        }
+        finish(h, nb0, 6);
+        {
+            Prof pf(h, MG_K_OTHER, 16.0 * N);
+            k_sub_mean<double><<<g0, blk, 0, s>>>(S.p, h->scal + 6, d0.nx, d0.ny, d0.nz);
+        }
+        // r32 of the next iteration is scaled by a power of two near the RMS of the
+        // residual just used (any power of two leaves the FP32 arithmetic unchanged)
+        S.scale = pow2_near(S.rho * S.norm_b / std::sqrt(N));
+        Prof pf(h, MG_K_REFINE, resid_bytes + 4.0 * N);
+        k_refine_residual<<<g0, blk, 0, s>>>(L64, S.p, h->bbar, 1.0 / S.scale, h->frhs[0], h->part);
+    }
+    finish(h, nb0, 4);
+    if (!f32) {
+        Prof pf(h, MG_K_OTHER, 16.0 * N);
+        k_sub_mean<double><<<g0, blk, 0, s>>>(S.p, h->scal + 5, d0.nx, d0.ny, d0.nz);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->host, h->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    return MG_OK;
+}
+
+// Step 3 (after the stream is synchronised): record the residual, test convergence.
+void solve_after_sync(SolveState& S) {
+    S.it++;
+    S.rho = std::sqrt(S.h->host[0]) / S.norm_b;
+    if (S.st.nhist < MG_MAX_HISTORY) S.st.history[S.st.nhist++] = S.rho;
+    if (!(S.rho == S.rho) || S.rho > 1e6 * S.rho0)
+        S.status = MG_E_DIVERGED;
+    else if (S.rho <= S.tol)
+        S.status = MG_OK;
+    else
+        S.status = MG_E_NOT_CONVERGED;
+}
+
+bool solve_running(const SolveState& S) {
+    return S.status == MG_E_NOT_CONVERGED && S.it < S.h->o.max_cycles;
+}
+
+// Step 4: statistics.
+void solve_end(SolveState& S, mg_stats* st) {
+    mg_handle* h = S.h;
+    S.st.outer = S.it;
+    if (h->o.precision == MG_FP64) S.st.cycles = S.it;
+    S.st.rel_residual = S.rho;
+    S.st.gamma = S.it > 0 && S.rho0 > 0 ? std::pow(S.rho / S.rho0, 1.0 / S.it) : 0.0;
+    S.st.status = S.status;
+    prof_collect(h);
+    for (int c = 0; c < MG_K_COUNT; c++) {
+        S.st.kernel_ms[c] = h->kernel_ms[c];
+        S.st.kernel_launches[c] = h->kernel_launches[c];
+        S.st.kernel_bytes[c] = h->kernel_bytes[c];
+    }
+    S.st.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - S.t0).count();
+    if (st) *st = S.st;
+}
+
+mg_status solve_impl(mg_handle* h, const double* rhs, double* p, double tol, mg_stats* st) {
+    SolveState S;
+    S.h = h;
+    S.rhs = rhs;
+    S.p = p;
+    S.tol = tol;
+    mg_status r = solve_begin(S);
+    if (r != MG_OK) return r;
+    while (solve_running(S)) {
+        r = solve_launch_iteration(S);
+        if (r != MG_OK) return r;
+        HIPCHK(hipStreamSynchronize(h->stream));
+        solve_after_sync(S);
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    solve_end(S, st);
+    if (S.status == MG_E_NOT_CONVERGED) set_error("max_cycles reached before the tolerance");
+    if (S.status == MG_E_DIVERGED) set_error("residual diverged");
+    return (mg_status)S.status;
+}
+
+const char* last_error() { return g_err.c_str(); }
+
+}  // namespace mgrt
+
+// ====================================================================== C ABI
+
+using namespace mgrt;
+
+extern "C" {
+
+mg_status mg_default_options(mg_options* o) {
+    if (!o) return MG_E_INVALID;
+    o->precision = MG_FP64;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->n_coarsest = 4;
+    o->inner_m = 1;
+    o->max_cycles = 100;
+    o->profile = 0;
+    return MG_OK;
+}
+
+mg_status mg_workspace_bytes(const mg_grid* g, const mg_options* o, size_t* bytes) {
+    if (!bytes) {
+        set_error("null argument");
+        return MG_E_INVALID;
+    }
+    Layout L;
+    mg_status r = plan(g, o, &L);
+    if (r != MG_OK) return r;
+    *bytes = L.total;
+    return MG_OK;
+}
+
+mg_status mg_setup(const mg_grid* g, const mg_options* o, const double* bx, const double* by, const double* bz,
+                   int bc, void* ws, size_t ws_bytes, void* stream, mg_handle** out) {
+    try {
+        if (!out || !bx || !by || !bz) {
+            set_error("null argument");
+            return MG_E_INVALID;
+        }
+        *out = nullptr;
+        if (bc != MG_BC_NEUMANN) {
+            set_error("only MG_BC_NEUMANN is supported");
+            return MG_E_INVALID;
+        }
+        mg_handle* h = new mg_handle();
+        h->g = *g;
+        h->o = *o;
+        mg_status r = plan(g, o, &h->L);
+        if (r != MG_OK) {
+            delete h;
+            return r;
+        }
+        if (!ws || ((uintptr_t)ws & 255) || ws_bytes < h->L.total) {
+            set_error("workspace missing, not 256-byte aligned, or smaller than mg_workspace_bytes");
+            delete h;
+            return MG_E_WORKSPACE;
+        }
+        h->ws = (char*)ws;
+        h->stream = (hipStream_t)stream;
+        if (hipHostMalloc((void**)&h->host, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            h->host = nullptr;
+            set_error("hipHostMalloc failed");
+            mg_destroy(h);
+            return MG_E_HIP;
+        }
+        r = setup_impl(h, bx, by, bz);
+        if (r != MG_OK) {
+            mg_destroy(h);
+            return r;
+        }
+        *out = h;
+        return MG_OK;
+    } catch (...) {
+        set_error("host exception in mg_setup");
+        return MG_E_HIP;
+    }
+}
+
+mg_status mg_solve(mg_handle* h, const double* rhs, double* p, double tol, mg_stats* st, void* stream) {
+    try {
+        if (!h || !rhs || !p || !(tol >= 0) || !std::isfinite(tol)) {
+            set_error("null handle/array or invalid tolerance");
+            return MG_E_INVALID;
+        }
+        h->stream = (hipStream_t)stream;
+        return solve_impl(h, rhs, p, tol, st);
+    } catch (...) {
+        set_error("host exception in mg_solve");
+        return MG_E_HIP;
+    }
+}
+
+void mg_destroy(mg_handle* h) {
+    if (!h) return;
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    if (h->host) (void)hipHostFree(h->host);
+    delete h;
+}
+
+mg_status mg_level_dims(const mg_handle* h, int l, int* nx, int* ny, int* nz) {
+    if (!h || l < 0 || l >= h->L.nlev || !nx || !ny || !nz) {
+        set_error("bad handle or level");
+        return MG_E_INVALID;
+    }
+    *nx = h->L.d[l].nx;
+    *ny = h->L.d[l].ny;
+    *nz = h->L.d[l].nz;
+    return MG_OK;
+}
+
+mg_status mg_copy_level(const mg_handle* h, int l, double* bx, double* by, double* bz, double* a, void* stream) {
+    if (!h || l < 0 || l >= h->L.nlev) {
+        set_error("bad handle or level");
+        return MG_E_INVALID;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const LevelDims& d = h->L.d[l];
+    if (bx) HIPCHK(hipMemcpyAsync(bx, h->bx[l], d.nfx() * 8, hipMemcpyDeviceToDevice, s));
+    if (by) HIPCHK(hipMemcpyAsync(by, h->by[l], d.nfy() * 8, hipMemcpyDeviceToDevice, s));
+    if (bz) HIPCHK(hipMemcpyAsync(bz, h->bz[l], d.nfz() * 8, hipMemcpyDeviceToDevice, s));
+    if (a) HIPCHK(hipMemcpyAsync(a, h->a[l], d.ncell() * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MG_OK;
+}
+
+const char* mg_status_string(mg_status s) {
+    switch (s) {
+        case MG_OK: return "MG_OK";
+        case MG_PENDING: return "MG_PENDING";
+        case MG_E_INVALID: return "MG_E_INVALID: invalid argument";
+        case MG_E_WORKSPACE: return "MG_E_WORKSPACE: workspace missing, misaligned or too small";
+        case MG_E_HIP: return "MG_E_HIP: HIP runtime error";
+        case MG_E_NOT_CONVERGED: return "MG_E_NOT_CONVERGED: tolerance not reached within max_cycles";
+        case MG_E_DIVERGED: return "MG_E_DIVERGED: residual diverged";
+        case MG_E_BUDGET: return "MG_E_BUDGET: request larger than the server arena";
+        case MG_E_NOT_FOUND: return "MG_E_NOT_FOUND: unknown ticket";
+    }
+    return "unknown status";
+}
+
+const char* mg_last_error(void) { return mgrt::last_error(); }
+
+}  // extern "C"

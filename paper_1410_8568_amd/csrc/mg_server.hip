@@ -1,0 +1,369 @@
+// Continuous-batching solve server.
+//
+// Requests arrive through mg_batch_submit from any thread.  A scheduler thread
+// admits them in arrival order as soon as (a) a slot is free and (b) their
+// workspace fits in the free part of the caller's HBM arena (first-fit), builds
+// their hierarchy in place (it stays resident until the request finishes) and
+// then advances every resident problem one outer iteration at a time.  Each
+// slot has its own HIP stream, so iterations of different problems overlap on
+// the device; a problem whose iteration has completed is tested for
+// convergence and relaunched immediately, without waiting for the others, and
+// a finished problem frees its slot and memory for the next waiting request.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "mg_core.h"
+
+using namespace mgrt;
+
+namespace {
+
+// First-fit allocator over [0, size) with coalescing frees.
+class Arena {
+   public:
+    void reset(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    bool alloc(size_t bytes, size_t* off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                size_t rest = it->second - bytes;
+                size_t at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t free_bytes() const {
+        size_t s = 0;
+        for (auto& kv : free_) s += kv.second;
+        return s;
+    }
+
+   private:
+    std::map<size_t, size_t> free_;
+};
+
+enum JobState { QUEUED, RUNNING, DONE };
+
+struct Job {
+    uint64_t ticket = 0;
+    mg_request req;
+    size_t bytes = 0, off = 0;
+    int slot = -1;
+    mg_handle* h = nullptr;
+    SolveState S;
+    hipEvent_t ev = nullptr;
+    JobState state = QUEUED;
+    mg_result result;
+};
+
+}  // namespace
+
+struct mg_server {
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    mg_server_options o;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Job*> queue;
+    std::unordered_map<uint64_t, Job*> jobs;
+    std::vector<Job*> active;
+    std::vector<hipStream_t> streams;
+    std::vector<int> slot_free;
+    std::vector<hipEvent_t> events;
+    Arena alloc;
+    std::thread th;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    std::chrono::steady_clock::time_point t0;
+
+    double now_ms() const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+void complete(mg_server* sv, Job* j, int status) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    j->result.status = status;
+    j->result.finish_ms = sv->now_ms();
+    j->state = DONE;
+    if (j->h) {
+        mg_destroy(j->h);
+        j->h = nullptr;
+    }
+    if (j->slot >= 0) {
+        sv->slot_free[j->slot] = 1;
+        j->slot = -1;
+    }
+    sv->alloc.release(j->off, j->bytes);
+}
+
+// Build the hierarchy and start the solve for an admitted job (scheduler thread).
+// Returns true if the job is running (needs iterations).
+bool start_job(mg_server* sv, Job* j) {
+    j->result.start_ms = sv->now_ms();
+    mg_handle* h = new mg_handle();
+    h->g = j->req.grid;
+    h->o = sv->o.solver;
+    h->o.profile = 0;
+    plan(&h->g, &h->o, &h->L);
+    h->ws = sv->arena + j->off;
+    h->stream = sv->streams[j->slot];
+    if (hipHostMalloc((void**)&h->host, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        h->host = nullptr;
+        delete h;
+        complete(sv, j, MG_E_HIP);
+        return false;
+    }
+    j->h = h;
+    mg_status r = setup_impl(h, j->req.bx, j->req.by, j->req.bz);
+    if (r != MG_OK) {
+        complete(sv, j, r);
+        return false;
+    }
+    j->S = SolveState();
+    j->S.h = h;
+    j->S.rhs = j->req.rhs;
+    j->S.p = j->req.p;
+    j->S.tol = j->req.tol;
+    r = solve_begin(j->S);
+    if (r != MG_OK) {
+        complete(sv, j, r);
+        return false;
+    }
+    if (!solve_running(j->S)) {
+        solve_end(j->S, &j->result.stats);
+        complete(sv, j, j->S.status);
+        return false;
+    }
+    return true;
+}
+
+bool launch(mg_server* sv, Job* j) {
+    if (solve_launch_iteration(j->S) != MG_OK) return false;
+    j->ev = sv->events[j->slot];
+    return hipEventRecord(j->ev, j->h->stream) == hipSuccess;
+}
+
+void scheduler(mg_server* sv) {
+    for (;;) {
+        // ---- admission, in arrival order
+        std::vector<Job*> admitted;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            if (sv->active.empty() && sv->queue.empty()) {
+                if (sv->stop) return;
+                sv->cv.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+                if (sv->stop && sv->queue.empty()) return;
+            }
+            while (!sv->queue.empty()) {
+                Job* j = sv->queue.front();
+                int slot = -1;
+                for (size_t s = 0; s < sv->slot_free.size(); s++)
+                    if (sv->slot_free[s]) {
+                        slot = (int)s;
+                        break;
+                    }
+                if (slot < 0) break;
+                size_t off;
+                if (!sv->alloc.alloc(j->bytes, &off)) break;
+                sv->queue.pop_front();
+                sv->slot_free[slot] = 0;
+                j->slot = slot;
+                j->off = off;
+                j->state = RUNNING;
+                admitted.push_back(j);
+            }
+        }
+        for (Job* j : admitted) {
+            if (start_job(sv, j)) {
+                if (launch(sv, j))
+                    sv->active.push_back(j);
+                else
+                    complete(sv, j, MG_E_HIP);
+            }
+        }
+        // ---- advance every resident problem whose iteration has finished
+        bool progressed = !admitted.empty();
+        for (size_t q = 0; q < sv->active.size();) {
+            Job* j = sv->active[q];
+            hipError_t e = hipEventQuery(j->ev);
+            if (e == hipErrorNotReady) {
+                q++;
+                continue;
+            }
+            progressed = true;
+            if (e != hipSuccess) {
+                complete(sv, j, MG_E_HIP);
+                sv->active.erase(sv->active.begin() + q);
+                continue;
+            }
+            solve_after_sync(j->S);
+            if (solve_running(j->S)) {
+                if (!launch(sv, j)) {
+                    complete(sv, j, MG_E_HIP);
+                    sv->active.erase(sv->active.begin() + q);
+                    continue;
+                }
+                q++;
+            } else {
+                solve_end(j->S, &j->result.stats);
+                complete(sv, j, j->S.status);
+                sv->active.erase(sv->active.begin() + q);
+            }
+        }
+        if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+mg_status mg_server_create(void* arena, size_t arena_bytes, const mg_server_options* o, mg_server** out) {
+    try {
+        if (!arena || !o || !out || ((uintptr_t)arena & 255) || arena_bytes == 0 || o->max_slots < 1 ||
+            o->max_slots > 256) {
+            set_error("null/misaligned arena, null options/out, or max_slots outside 1..256");
+            return MG_E_INVALID;
+        }
+        mg_grid probe{8, 8, 8};
+        Layout L;
+        mg_status r = plan(&probe, &o->solver, &L);
+        if (r != MG_OK) return r;
+        mg_server* sv = new mg_server();
+        sv->arena = (char*)arena;
+        sv->arena_bytes = arena_bytes;
+        sv->o = *o;
+        sv->alloc.reset(arena_bytes & ~(size_t)255);
+        sv->t0 = std::chrono::steady_clock::now();
+        for (int s = 0; s < o->max_slots; s++) {
+            hipStream_t st;
+            hipEvent_t ev;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                set_error("stream/event creation failed");
+                for (auto x : sv->streams) (void)hipStreamDestroy(x);
+                for (auto x : sv->events) (void)hipEventDestroy(x);
+                delete sv;
+                return MG_E_HIP;
+            }
+            sv->streams.push_back(st);
+            sv->events.push_back(ev);
+            sv->slot_free.push_back(1);
+        }
+        sv->th = std::thread(scheduler, sv);
+        *out = sv;
+        return MG_OK;
+    } catch (...) {
+        set_error("host exception in mg_server_create");
+        return MG_E_HIP;
+    }
+}
+
+mg_status mg_batch_submit(mg_server* sv, const mg_request* r, uint64_t* ticket) {
+    try {
+        if (!sv || !r || !ticket || !r->bx || !r->by || !r->bz || !r->rhs || !r->p || !(r->tol >= 0)) {
+            set_error("null server/request/array or bad tolerance");
+            return MG_E_INVALID;
+        }
+        Layout L;
+        mg_status st = plan(&r->grid, &sv->o.solver, &L);
+        if (st != MG_OK) return st;
+        size_t bytes = (L.total + 255) & ~(size_t)255;
+        if (bytes > (sv->arena_bytes & ~(size_t)255)) {
+            set_error("request workspace " + std::to_string(bytes) + " B exceeds the arena");
+            return MG_E_BUDGET;
+        }
+        Job* j = new Job();
+        j->req = *r;
+        j->bytes = bytes;
+        memset(&j->result, 0, sizeof j->result);
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            if (sv->stop) {
+                delete j;
+                set_error("server is shutting down");
+                return MG_E_INVALID;
+            }
+            j->ticket = sv->next_ticket++;
+            j->result.submit_ms = sv->now_ms();
+            sv->jobs[j->ticket] = j;
+            sv->queue.push_back(j);
+        }
+        sv->cv.notify_one();
+        *ticket = j->ticket;
+        return MG_OK;
+    } catch (...) {
+        set_error("host exception in mg_batch_submit");
+        return MG_E_HIP;
+    }
+}
+
+mg_status mg_poll(mg_server* sv, uint64_t ticket, mg_result* out) {
+    if (!sv) {
+        set_error("null server");
+        return MG_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->jobs.find(ticket);
+    if (it == sv->jobs.end()) {
+        set_error("unknown ticket");
+        return MG_E_NOT_FOUND;
+    }
+    Job* j = it->second;
+    if (j->state != DONE) return MG_PENDING;
+    if (out) *out = j->result;
+    mg_status s = (mg_status)j->result.status;
+    sv->jobs.erase(it);
+    delete j;
+    return s;
+}
+
+void mg_server_destroy(mg_server* sv) {
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv.notify_all();
+    if (sv->th.joinable()) sv->th.join();
+    for (auto& kv : sv->jobs) delete kv.second;
+    for (auto x : sv->streams) (void)hipStreamDestroy(x);
+    for (auto x : sv->events) (void)hipEventDestroy(x);
+    delete sv;
+}
+
+}  // extern "C"

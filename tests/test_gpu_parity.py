@@ -1,0 +1,162 @@
+"""GPU parity: the HIP library (called through its C ABI) against the CPU oracle.
+
+Bars: setup arrays (coarsened faces, cell weights) bit-exact; per-cycle relative
+residual histories equal to rounding; the final p within 1e-8 relative L2 of the
+oracle's p with a final relative residual <= 1e-10.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import pins
+from gpu_util import check_history, gpu_solve, rel
+from paper_1410_8568_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1410_8568_amd import mg
+    mg.lib()
+
+
+def ragged_problem(n, seed=21, ratio=1000.0):
+    """Non-cubic grid with a sphere and random N(0,1) rhs (cells are cubic in index space)."""
+    nx, ny, nz = n
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid((np.arange(nz) + .5) / nz, (np.arange(ny) + .5) / ny, (np.arange(nx) + .5) / nx,
+                          indexing="ij")
+    phi = 0.3 - np.sqrt((x - .4) ** 2 + (y - .6) ** 2 + (z - .5) ** 2)
+    ind = inputs.smoothed_heaviside(phi, 1.5 / max(n))
+    alpha = 1.0 / (1.0 + (ratio - 1.0) * ind)
+    bx, by, bz = inputs.faces_from_alpha(alpha)
+    return inputs.Problem(n, bx, by, bz, rng.standard_normal((nz, ny, nx)), dict(kind="ragged"))
+
+
+@pytest.mark.parametrize("n,nc", [((32, 32, 32), 4), ((40, 24, 12), 4), ((96, 96, 96), 8)])
+def test_setup_hierarchy_bit_exact(n, nc):
+    import torch
+    from paper_1410_8568_amd import mg
+    P = ragged_problem(n) if n[0] != 96 else inputs.batch_problems(1, sizes=(96,), build=True)[0]
+    bx, by, bz, _ = mg.to_device(P)
+    S = mg.Solver(bx, by, bz, n_coarsest=nc)
+    levels = S.levels()
+    assert levels == oracle.plan(n, nc)
+    for l in range(len(levels)):
+        g = [t.cpu().numpy() for t in S.level_arrays(l)]
+        o = oracle.hierarchy_level(P.bx, P.by, P.bz, nc, l)
+        for name, a, b in zip("xyza", g, o):
+            assert np.array_equal(a, b), (l, name, np.abs(a - b).max())
+    S.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_config0_matches_oracle(precision):
+    P = inputs.config0()
+    ref = oracle.solve(P.bx, P.by, P.bz, P.b, tol=1e-10, n_coarsest=4, precision=precision)
+    p, st = gpu_solve(P, precision=precision, tol=1e-10, n_coarsest=4)
+    assert st["rc"] == 0, st
+    assert st["history"][-1] <= 1e-10
+    check_history(st["history"], ref["history"], precision)
+    assert rel(p, ref["p"]) <= 1e-8
+    assert abs(p.mean()) <= 1e-12 * np.abs(p).max()
+    # against the independent direct solve as well
+    assert rel(p, pins.bordered_direct_solve(P.bx, P.by, P.bz, P.b)) <= 1e-8
+    assert np.isclose(st["gamma"], ref["gamma"], rtol=1e-6)
+
+
+@pytest.mark.parametrize("n,nc", [((40, 24, 12), 4), ((48, 48, 48), 4), ((96, 96, 96), 8), ((6, 10, 4), 4),
+                                  ((2, 2, 2), 4), ((5, 7, 3), 4)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_ragged_and_small_grids(n, nc, precision):
+    P = ragged_problem(n)
+    ref = oracle.solve(P.bx, P.by, P.bz, P.b, tol=1e-10, n_coarsest=nc, precision=precision)
+    p, st = gpu_solve(P, precision=precision, tol=1e-10, n_coarsest=nc)
+    assert st["rc"] == 0, st
+    check_history(st["history"], ref["history"], precision)
+    assert rel(p, ref["p"]) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_batch_scene_problems(precision):
+    for P in inputs.batch_problems(3, sizes=(32, 64)):
+        ref = oracle.solve(P.bx, P.by, P.bz, P.b, tol=1e-10, precision=precision)
+        p, st = gpu_solve(P, precision=precision, tol=1e-10)
+        assert st["rc"] == 0
+        check_history(st["history"], ref["history"], precision)
+        assert rel(p, ref["p"]) <= 1e-8
+
+
+def test_layered_closed_form_256():
+    """Full-size property check: z-only coefficients and rhs, exact 1-D solution."""
+    P = inputs.layered_problem(256)
+    p, st = gpu_solve(P, tol=1e-10, max_cycles=100)
+    assert st["rc"] == 0, st["history"]
+    p1 = pins.layered_solve(P.bz[:, 0, 0], P.b[:, 0, 0])
+    assert rel(p, np.broadcast_to(p1[:, None, None], p.shape)) <= 1e-8
+
+
+def test_constant_coefficient_dct_128():
+    P = inputs.constant_problem(128, beta=0.7)
+    for precision in ("fp64", "fp32_refined"):
+        p, st = gpu_solve(P, precision=precision, tol=1e-12)
+        assert st["rc"] == 0, st
+        assert rel(p, pins.dct_solve(P.b, beta=0.7)) <= 1e-9
+
+
+def test_config1_full_size_matches_oracle():
+    """256^3 drop splash, the FP64 workload: per-cycle history and final p vs the oracle."""
+    P = inputs.config1(256)
+    ref = oracle.solve(P.bx, P.by, P.bz, P.b, tol=1e-10)
+    for precision in ("fp64", "fp32_refined"):
+        p, st = gpu_solve(P, precision=precision, tol=1e-10)
+        assert st["rc"] == 0, st
+        assert st["history"][-1] <= 1e-10
+        if precision == "fp64":
+            check_history(st["history"], ref["history"])
+        assert rel(p, ref["p"]) <= 1e-8
+
+
+def test_zero_rhs_and_warm_start():
+    import torch
+    from paper_1410_8568_amd import mg
+    P = inputs.config0()
+    bx, by, bz, b = mg.to_device(P)
+    S = mg.Solver(bx, by, bz)
+    p = torch.full_like(b, 5.0)
+    st = S.solve(torch.full_like(b, 2.0), p)
+    assert st["rc"] == 0 and torch.count_nonzero(p).item() == 0
+    p.zero_()
+    st = S.solve(b, p, tol=1e-10)
+    st2 = S.solve(b, p, tol=1e-10)
+    assert st2["rc"] == 0 and st2["cycles"] == 0
+    S.close()
+
+
+def test_error_paths():
+    import torch
+    from paper_1410_8568_amd import mg
+    P = inputs.config0()
+    bx, by, bz, b = mg.to_device(P)
+    bad = bx.clone()
+    bad[3, 4, 5] = -1.0
+    with pytest.raises(mg.MGError) as ei:
+        mg.Solver(bad, by, bz)
+    assert ei.value.status == mg.MG_E_INVALID
+    bad[3, 4, 5] = float("nan")
+    with pytest.raises(mg.MGError):
+        mg.Solver(bad, by, bz)
+    # coarsest grid too large: odd 9^3 = 729 cells
+    P9 = ragged_problem((9, 9, 9))
+    with pytest.raises(mg.MGError):
+        mg.Solver(*mg.to_device(P9)[:3])
+    # not converged within max_cycles: p is the last iterate, status reported
+    S = mg.Solver(bx, by, bz, max_cycles=2)
+    p = torch.zeros_like(b)
+    st = S.solve(b, p, tol=1e-10, check=False)
+    assert st["rc"] == mg.MG_E_NOT_CONVERGED and st["cycles"] == 2
+    S.close()
