@@ -77,7 +77,19 @@ typedef struct {
     int inner_m;     /* FP32 V-cycles per FP64 outer iteration (refined mode, default 1) */
     int max_cycles;  /* V-cycles (FP64) or outer iterations (refined), default 100 */
     int profile;     /* nonzero: time every kernel launch with HIP events (stats.kernel_*) */
+    int tile;        /* smoother kernel: 0 = automatic (each level's variant is chosen by
+                        timing every variant at setup; choices are cached per grid size and
+                        precision, in memory and, if the environment variable MG_TUNE_CACHE
+                        names a file, in that JSON-lines file), -1 = reference
+                        one-colour-per-pass kernels on every level, 1..MG_NUM_TILES = one fixed
+                        variant of the fused red-black sweep on every level that has a
+                        ping-pong buffer.  Every choice gives bit-identical results. */
 } mg_options;
+
+/* Fused sweep variants: tile (cells) 64x4, 64x8, 64x12, 32x8, each with a
+   target of about 1024 (odd) or 4096 (even) workgroups: variant v uses tile
+   (v-1)/2 and target (v-1)%2. */
+#define MG_NUM_TILES 8
 
 /* Kernel classes reported in mg_stats when options.profile is set. */
 enum {
@@ -158,6 +170,10 @@ void mg_destroy(mg_handle *h);
 
 /* Hierarchy inspection (for tests): number of levels and dims of level l. */
 mg_status mg_level_dims(const mg_handle *h, int l, int *nx, int *ny, int *nz);
+
+/* Smoother variant used on level l (-1 reference, 1..MG_NUM_TILES fused; the
+   coarsest level, which is not smoothed, reports 0). */
+mg_status mg_level_tile(const mg_handle *h, int l, int *tile);
 
 /*
  * Copy level l's FP64 faces and cell weights into caller device buffers of the

@@ -30,6 +30,7 @@ struct Layout {
     LevelDims d[MG_MAX_LEVELS];
     size_t bx[MG_MAX_LEVELS], by[MG_MAX_LEVELS], bz[MG_MAX_LEVELS], a[MG_MAX_LEVELS];
     size_t e[MG_MAX_LEVELS], rhs[MG_MAX_LEVELS];                  // FP64 levels >= 1 (FP64 mode)
+    size_t tmp[MG_MAX_LEVELS], ftmp[MG_MAX_LEVELS];               // ping-pong buffers of the fused sweep
     size_t fbx[MG_MAX_LEVELS], fby[MG_MAX_LEVELS], fbz[MG_MAX_LEVELS], fa[MG_MAX_LEVELS];
     size_t fe[MG_MAX_LEVELS], frhs[MG_MAX_LEVELS];                // FP32 levels (refined mode)
     size_t bbar = 0, binv = 0, scal = 0, part = 0, flag = 0;
@@ -55,6 +56,8 @@ struct mg_handle {
     double *e[MG_MAX_LEVELS], *rhs[MG_MAX_LEVELS];
     float *fbx[MG_MAX_LEVELS], *fby[MG_MAX_LEVELS], *fbz[MG_MAX_LEVELS], *fa[MG_MAX_LEVELS];
     float *fe[MG_MAX_LEVELS], *frhs[MG_MAX_LEVELS];
+    double* tmp[MG_MAX_LEVELS];
+    float* ftmp[MG_MAX_LEVELS];
     double* bbar = nullptr;
     double* binv = nullptr;
     double* scal = nullptr;
@@ -62,6 +65,7 @@ struct mg_handle {
     int* flag = nullptr;
     hipStream_t stream = nullptr;
     double* host = nullptr;  // pinned host copy of device scalars
+    int tile[MG_MAX_LEVELS];  // smoother variant per level
     // profiling
     struct Rec {
         int cls;

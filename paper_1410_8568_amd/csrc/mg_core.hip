@@ -9,7 +9,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -48,6 +51,37 @@ static int col_blocks(int nx, int ny, int nz) {
     return (int)(g.x * g.y * g.z);
 }
 
+// Tiles (32 x 8 fine columns) and even-length z-chunks of the restriction kernel.
+static ColGrid rgrid(int nx, int ny, int nz, int* nblocks) {
+    ColGrid G;
+    G.tiles_x = (nx + RBX - 1) / RBX;
+    G.tiles_y = (ny + RBY - 1) / RBY;
+    const int tiles = G.tiles_x * G.tiles_y;
+    int chunks = std::max(1, std::min(std::max(1, nz / 16), (2048 + tiles - 1) / tiles));
+    int kc = (nz + chunks - 1) / chunks;
+    if (kc & 1) kc++;
+    G.kc = kc;
+    chunks = (nz + kc - 1) / kc;
+    *nblocks = tiles * chunks;
+    return G;
+}
+
+// Tiles and z-chunks of the z-marching column kernels: about 2048 workgroups,
+// chunks of >= 16 planes (an even count when `even`).
+static ColGrid zgrid(int cols_x, int cols_y, int nz, bool even, int* nblocks) {
+    ColGrid G;
+    G.tiles_x = (cols_x + CBX - 1) / CBX;
+    G.tiles_y = (cols_y + CBY - 1) / CBY;
+    const int tiles = G.tiles_x * G.tiles_y;
+    int chunks = std::max(1, std::min(std::max(1, nz / 16), (2048 + tiles - 1) / tiles));
+    int kc = (nz + chunks - 1) / chunks;
+    if (even && (kc & 1)) kc++;
+    G.kc = kc;
+    chunks = (nz + kc - 1) / kc;
+    *nblocks = tiles * chunks;
+    return G;
+}
+
 mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
     if (!g || !o || !L) {
         set_error("null argument");
@@ -66,7 +100,8 @@ mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
         return MG_E_INVALID;
     }
     if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 16 || o->nu2 > 16 || o->n_coarsest < 1 || o->inner_m < 1 ||
-        o->inner_m > 16 || o->max_cycles < 1 || o->max_cycles > MG_MAX_HISTORY - 1) {
+        o->inner_m > 16 || o->max_cycles < 1 || o->max_cycles > MG_MAX_HISTORY - 1 || o->tile < -1 ||
+        o->tile > MG_NUM_TILES) {
         set_error("option out of range");
         return MG_E_INVALID;
     }
@@ -111,6 +146,7 @@ mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
             L->e[l] = take(ld.ncell() * 8);
             L->rhs[l] = take(ld.ncell() * 8);
         }
+        if (!f32 && l < L->nlev - 1) L->tmp[l] = take(ld.ncell() * 8);
         if (f32) {
             L->fbx[l] = take(ld.nfx() * 4);
             L->fby[l] = take(ld.nfy() * 4);
@@ -118,13 +154,18 @@ mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
             L->fa[l] = take(ld.ncell() * 4);
             L->fe[l] = take(ld.ncell() * 4);
             L->frhs[l] = take(ld.ncell() * 4);
+            if (l < L->nlev - 1) L->ftmp[l] = take(ld.ncell() * 4);
         }
     }
     L->bbar = take(L->d[0].ncell() * 8);
     L->binv = take((size_t)L->ncoarse * L->ncoarse * 8);
     L->scal = take(64 * 8);
     int mb = 0;
-    for (int l = 0; l < L->nlev; l++) mb = std::max(mb, col_blocks(L->d[l].nx, L->d[l].ny, L->d[l].nz));
+    for (int l = 0; l < L->nlev; l++) {
+        int zb = 0;
+        zgrid(L->d[l].nx, L->d[l].ny, L->d[l].nz, false, &zb);
+        mb = std::max(mb, std::max(zb, col_blocks(L->d[l].nx, L->d[l].ny, L->d[l].nz)));
+    }
     L->max_blocks = mb;
     L->part = take((size_t)2 * mb * 8);
     L->flag = take(64);
@@ -180,6 +221,9 @@ static void prof_collect(mg_handle* h) {
 
 // ------------------------------------------------------------------ setup
 
+template <class T>
+static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b, int* choice);
+
 static void bind(mg_handle* h) {
     const Layout& L = h->L;
     char* w = h->ws;
@@ -191,6 +235,8 @@ static void bind(mg_handle* h) {
         h->a[l] = (double*)(w + L.a[l]);
         h->e[l] = (l > 0 && !f32) ? (double*)(w + L.e[l]) : nullptr;
         h->rhs[l] = (l > 0 && !f32) ? (double*)(w + L.rhs[l]) : nullptr;
+        h->tmp[l] = (!f32 && l < L.nlev - 1) ? (double*)(w + L.tmp[l]) : nullptr;
+        h->ftmp[l] = (f32 && l < L.nlev - 1) ? (float*)(w + L.ftmp[l]) : nullptr;
         if (f32) {
             h->fbx[l] = (float*)(w + L.fbx[l]);
             h->fby[l] = (float*)(w + L.fby[l]);
@@ -245,6 +291,26 @@ mg_status setup_impl(mg_handle* h, const double* bx, const double* by, const dou
         }
         HIPCHK(hipGetLastError());
     }
+    // smoother variant per level
+    for (int l = 0; l < MG_MAX_LEVELS; l++) h->tile[l] = 0;
+    for (int l = 0; l + 1 < L.nlev; l++) {
+        if (h->o.tile != 0) {
+            h->tile[l] = h->o.tile;
+            continue;
+        }
+        const LevelDims& d = L.d[l];
+        mg_status r;
+        if (h->o.precision == MG_FP32_REFINED) {
+            Lvl<float> lv{d.nx, d.ny, d.nz, h->fbx[l], h->fby[l], h->fbz[l]};
+            r = tune_level<float>(h, lv, h->fe[l], h->ftmp[l], h->frhs[l], &h->tile[l]);
+        } else {
+            Lvl<double> lv{d.nx, d.ny, d.nz, h->bx[l], h->by[l], h->bz[l]};
+            double* pin = l == 0 ? h->bbar : h->e[l];
+            double* b = l == 0 ? h->bbar : h->rhs[l];
+            r = tune_level<double>(h, lv, pin, h->tmp[l], b, &h->tile[l]);
+        }
+        if (r != MG_OK) return r;
+    }
     int flags[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(flags, h->flag, sizeof flags, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -268,12 +334,162 @@ struct Hier {
     Lvl<T> L[MG_MAX_LEVELS];
     T* e[MG_MAX_LEVELS];
     T* rhs[MG_MAX_LEVELS];
+    T* tmp[MG_MAX_LEVELS];
     const T* a[MG_MAX_LEVELS];
 };
 
+template <class T, int TX, int TY>
+static void launch_sweep(hipStream_t s, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0, int target) {
+    const int gx = (L.nx + TX - 1) / TX, gy = (L.ny + TY - 1) / TY;
+    const int tiles = gx * gy;
+    // chunks of >= 8 planes, so the redundant planes at chunk ends stay a small fraction
+    int chunks = std::max(1, std::min(std::max(1, L.nz / 8), (target + tiles - 1) / tiles));
+    const int kc = (L.nz + chunks - 1) / chunks;
+    chunks = (L.nz + kc - 1) / kc;
+    k_rb_sweep<T, TX, TY><<<dim3(tiles * chunks), (TX + 2) * (TY + 2), 0, s>>>(L, pin, pout, b, c0, kc, gx, gy);
+}
+
+// Fused sweep variant v in 1..MG_NUM_TILES.
 template <class T>
-static double nbytes_sweep_half(const LevelDims& d) {
-    return 0.5 * ((3.0 * d.ncell() + d.nfaces()) * sizeof(T));
+static void fused_sweep(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0) {
+    const int target = ((v - 1) & 1) ? 4096 : 1024;
+    switch ((v - 1) >> 1) {
+        case 0: launch_sweep<T, 64, 4>(s, L, pin, pout, b, c0, target); break;
+        case 1: launch_sweep<T, 64, 8>(s, L, pin, pout, b, c0, target); break;
+        case 2: launch_sweep<T, 64, 12>(s, L, pin, pout, b, c0, target); break;
+        default: launch_sweep<T, 32, 8>(s, L, pin, pout, b, c0, target); break;
+    }
+}
+
+template <class T>
+static void ref_sweep(hipStream_t s, const Lvl<T>& L, T* p, const T* b, int c0) {
+    const dim3 g = col_grid(L.nx, L.ny, L.nz), blk(BX, BY);
+    k_rb_half<T><<<g, blk, 0, s>>>(L, p, b, c0);
+    k_rb_half<T><<<g, blk, 0, s>>>(L, p, b, 1 - c0);
+}
+
+// ------------------------------------------------------------------ smoother tuning
+//
+// For every smoothed level the variant with the shortest measured sweep is
+// chosen at setup (each variant: one warm-up and three timed sweeps on the
+// level's own scratch buffers, zero-filled), and remembered per (precision,
+// grid size) for the life of the process and, when MG_TUNE_CACHE names a file,
+// across processes (one JSON object per line).
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::array<int, 4>, int> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = getenv("MG_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        int pr, x, y, z, v;
+        if (sscanf(line, "{\"bytes\": %d, \"nx\": %d, \"ny\": %d, \"nz\": %d, \"variant\": %d}", &pr, &x, &y, &z,
+                   &v) == 5 &&
+            v >= -1 && v <= MG_NUM_TILES && v != 0)
+            g_tune[{pr, x, y, z}] = v;
+    }
+    fclose(f);
+}
+
+void tune_store_locked(const std::array<int, 4>& k, int v) {
+    g_tune[k] = v;
+    const char* path = getenv("MG_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "{\"bytes\": %d, \"nx\": %d, \"ny\": %d, \"nz\": %d, \"variant\": %d}\n", k[0], k[1], k[2], k[3], v);
+    fclose(f);
+}
+}  // namespace
+
+template <class T>
+static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b, int* choice) {
+    const std::array<int, 4> key{(int)sizeof(T), L.nx, L.ny, L.nz};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            *choice = it->second;
+            return MG_OK;
+        }
+    }
+    hipStream_t s = h->stream;
+    const size_t n = (size_t)L.nx * L.ny * L.nz;
+    HIPCHK(hipMemsetAsync(pin, 0, n * sizeof(T), s));
+    if (b != pin) HIPCHK(hipMemsetAsync(b, 0, n * sizeof(T), s));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bestv = -1;
+    for (int v = -1; v <= MG_NUM_TILES; v++) {
+        if (v == 0) continue;
+        auto run = [&]() {
+            if (v < 0)
+                ref_sweep<T>(s, L, pin, b, 0);
+            else
+                fused_sweep<T>(s, v, L, pin, pout, b, 0);
+        };
+        run();
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 3; rep++) {
+            (void)hipEventRecord(e0, s);
+            run();
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            tmin = std::min(tmin, ms);
+        }
+        if (tmin < best) {
+            best = tmin;
+            bestv = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipGetLastError());
+    *choice = bestv;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_store_locked(key, bestv);
+    return MG_OK;
+}
+
+// nsweep red-black sweeps on level l, first colour c0 (0: red first).
+template <class T>
+static void smooth(mg_handle* h, Hier<T>& H, int l, int nsweep, int c0) {
+    if (nsweep <= 0) return;
+    hipStream_t s = h->stream;
+    const LevelDims& d = H.d[l];
+    const int cls = l == 0 ? MG_K_SMOOTH_FINE : MG_K_SMOOTH;
+    const double full = (3.0 * d.ncell() + d.nfaces()) * sizeof(T);
+    const int tile = H.tmp[l] ? h->tile[l] : -1;
+    int rem = nsweep;
+    if (tile < 0 || (rem & 1)) {
+        const int n_ref = tile < 0 ? rem : 1;
+        for (int it = 0; it < n_ref; it++) {
+            Prof pf(h, cls, full);
+            ref_sweep<T>(s, H.L[l], H.e[l], H.rhs[l], c0);
+        }
+        rem -= n_ref;
+    }
+    for (; rem >= 2; rem -= 2) {
+        {
+            Prof pf(h, cls, full);
+            fused_sweep<T>(s, tile, H.L[l], H.e[l], H.tmp[l], H.rhs[l], c0);
+        }
+        Prof pf(h, cls, full);
+        fused_sweep<T>(s, tile, H.L[l], H.tmp[l], H.e[l], H.rhs[l], c0);
+    }
 }
 
 template <class T>
@@ -286,18 +502,13 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l) {
         return;
     }
     const dim3 g = col_grid(d.nx, d.ny, d.nz), blk(BX, BY);
-    const double hb = nbytes_sweep_half<T>(d);
-    const int cls_s = MG_K_SMOOTH;
-    for (int it = 0; it < h->o.nu1; it++) {
-        for (int colour = 0; colour < 2; colour++) {
-            Prof pf(h, l == 0 ? MG_K_SMOOTH_FINE : cls_s, hb);
-            k_rb_half<T><<<g, blk, 0, s>>>(H.L[l], H.e[l], H.rhs[l], colour);
-        }
-    }
+    smooth(h, H, l, h->o.nu1, 0);
     const LevelDims& c = H.d[l + 1];
     {
         Prof pf(h, MG_K_RESTRICT, ((2.0 * d.ncell() + d.nfaces()) + c.ncell()) * sizeof(T));
-        k_residual_restrict<T><<<col_grid(c.nx, c.ny, c.nz), blk, 0, s>>>(H.L[l], H.e[l], H.rhs[l], H.rhs[l + 1]);
+        int nb = 0;
+        const ColGrid G = rgrid(d.nx, d.ny, d.nz, &nb);
+        k_resid_restrict_col<T><<<nb, 256, 0, s>>>(H.L[l], H.e[l], H.rhs[l], G, H.rhs[l + 1]);
     }
     {
         Prof pf(h, MG_K_OTHER, (double)c.ncell() * sizeof(T));
@@ -308,12 +519,7 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l) {
         Prof pf(h, MG_K_PROLONG, (2.0 * d.ncell() + 2.0 * c.ncell()) * sizeof(T));
         k_prolong_add<T><<<g, blk, 0, s>>>(H.e[l + 1], H.a[l + 1], c.nx, c.ny, c.nz, H.e[l]);
     }
-    for (int it = 0; it < h->o.nu2; it++) {
-        for (int colour = 1; colour >= 0; colour--) {
-            Prof pf(h, l == 0 ? MG_K_SMOOTH_FINE : cls_s, hb);
-            k_rb_half<T><<<g, blk, 0, s>>>(H.L[l], H.e[l], H.rhs[l], colour);
-        }
-    }
+    smooth(h, H, l, h->o.nu2, 1);
 }
 
 static double pow2_near(double v) {
@@ -336,11 +542,13 @@ static void build_hier(mg_handle* h, double* p, Hier<double>& H64, Hier<float>& 
         H64.L[l] = Lvl<double>{d.nx, d.ny, d.nz, h->bx[l], h->by[l], h->bz[l]};
         H64.e[l] = l == 0 ? p : h->e[l];
         H64.rhs[l] = l == 0 ? h->bbar : h->rhs[l];
+        H64.tmp[l] = h->tmp[l];
         H64.a[l] = h->a[l];
         if (h->o.precision == MG_FP32_REFINED) {
             H32.L[l] = Lvl<float>{d.nx, d.ny, d.nz, h->fbx[l], h->fby[l], h->fbz[l]};
             H32.e[l] = h->fe[l];
             H32.rhs[l] = h->frhs[l];
+            H32.tmp[l] = h->ftmp[l];
             H32.a[l] = h->fa[l];
         }
     }
@@ -388,14 +596,16 @@ mg_status solve_begin(SolveState& S) {
     }
     const double resid_bytes = (2.0 * N + d0.nfaces()) * 8.0;
     S.scale = pow2_near(S.norm_b / std::sqrt(N));
+    int nbz = 0;
+    const ColGrid G0 = zgrid(d0.nx, d0.ny, d0.nz, false, &nbz);
     if (f32) {
         Prof pf(h, MG_K_REFINE, resid_bytes + 4.0 * N);
-        k_refine_residual<<<g0, blk, 0, s>>>(L64, S.p, h->bbar, 1.0 / S.scale, h->frhs[0], h->part);
+        k_resid_col<double, 1><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, 1.0 / S.scale, h->frhs[0], h->part);
     } else {
         Prof pf(h, MG_K_NORM, resid_bytes);
-        k_resid_norm<double><<<g0, blk, 0, s>>>(L64, S.p, h->bbar, h->part);
+        k_resid_col<double, 0><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, 1.0, nullptr, h->part);
     }
-    finish(h, nb0, 4);
+    finish(h, nbz, 4);
     {
         Prof pf(h, MG_K_OTHER, 16.0 * N);
         k_sub_mean<double><<<g0, blk, 0, s>>>(S.p, h->scal + 5, d0.nx, d0.ny, d0.nz);
@@ -427,11 +637,13 @@ mg_status solve_launch_iteration(SolveState& S) {
     Hier<double> H64;
     Hier<float> H32;
     build_hier(h, S.p, H64, H32);
+    int nbz = 0;
+    const ColGrid G0 = zgrid(d0.nx, d0.ny, d0.nz, false, &nbz);
     if (!f32) {
         vcycle(h, H64, 0);
         S.st.cycles++;
         Prof pf(h, MG_K_NORM, resid_bytes);
-        k_resid_norm<double><<<g0, blk, 0, s>>>(L64, S.p, h->bbar, h->part);
+        k_resid_col<double, 0><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, 1.0, nullptr, h->part);
     } else {
         {
             Prof pf(h, MG_K_OTHER, 4.0 * N);
@@ -454,9 +666,9 @@ mg_status solve_launch_iteration(SolveState& S) {
         // residual just used (any power of two leaves the FP32 arithmetic unchanged)
         S.scale = pow2_near(S.rho * S.norm_b / std::sqrt(N));
         Prof pf(h, MG_K_REFINE, resid_bytes + 4.0 * N);
-        k_refine_residual<<<g0, blk, 0, s>>>(L64, S.p, h->bbar, 1.0 / S.scale, h->frhs[0], h->part);
+        k_resid_col<double, 1><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, 1.0 / S.scale, h->frhs[0], h->part);
     }
-    finish(h, nb0, 4);
+    finish(h, nbz, 4);
     if (!f32) {
         Prof pf(h, MG_K_OTHER, 16.0 * N);
         k_sub_mean<double><<<g0, blk, 0, s>>>(S.p, h->scal + 5, d0.nx, d0.ny, d0.nz);
@@ -541,6 +753,7 @@ mg_status mg_default_options(mg_options* o) {
     o->inner_m = 1;
     o->max_cycles = 100;
     o->profile = 0;
+    o->tile = 0;
     return MG_OK;
 }
 
@@ -631,6 +844,15 @@ mg_status mg_level_dims(const mg_handle* h, int l, int* nx, int* ny, int* nz) {
     *nx = h->L.d[l].nx;
     *ny = h->L.d[l].ny;
     *nz = h->L.d[l].nz;
+    return MG_OK;
+}
+
+mg_status mg_level_tile(const mg_handle* h, int l, int* tile) {
+    if (!h || l < 0 || l >= h->L.nlev || !tile) {
+        set_error("bad handle or level");
+        return MG_E_INVALID;
+    }
+    *tile = h->tile[l];
     return MG_OK;
 }
 

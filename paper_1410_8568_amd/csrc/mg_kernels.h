@@ -37,8 +37,29 @@ struct Lvl {
     const T* bz;
 };
 
+// Gauss-Seidel update value and the neighbour sum of eq. (10) from the six face
+// coefficients and neighbour values, faces in the order x-, x+, y-, y+, z-, z+.
+// Explicit fma order, so every kernel that evaluates the stencil (fused or not)
+// produces bit-identical results.
+template <class T>
+__device__ __forceinline__ T stencil_sum(T w0, T w1, T w2, T w3, T w4, T w5, T p0, T p1, T p2, T p3, T p4,
+                                         T p5) {
+    T acc = w0 * p0;
+    acc = fma(w1, p1, acc);
+    acc = fma(w2, p2, acc);
+    acc = fma(w3, p3, acc);
+    acc = fma(w4, p4, acc);
+    acc = fma(w5, p5, acc);
+    return acc;
+}
+
+template <class T>
+__device__ __forceinline__ T stencil_diag(T w0, T w1, T w2, T w3, T w4, T w5) {
+    return ((((w0 + w1) + w2) + w3) + w4) + w5;
+}
+
 // Neighbour sum s = sum_f beta_f p_nb and diagonal d = sum_f beta_f for cell
-// (i,j,k) of eq. (10); faces visited x-, x+, y-, y+, z-, z+.
+// (i,j,k); out-of-grid neighbours read as 0 (their face coefficient is 0).
 template <class T>
 __device__ __forceinline__ void nbsum(const Lvl<T>& L, const T* __restrict__ p, int i, int j, int k,
                                       T& s, T& d) {
@@ -53,14 +74,8 @@ __device__ __forceinline__ void nbsum(const Lvl<T>& L, const T* __restrict__ p, 
     T p3 = j < ny - 1 ? p[c + nx] : T(0);
     T p4 = k > 0 ? p[c - (size_t)nx * ny] : T(0);
     T p5 = k < nz - 1 ? p[c + (size_t)nx * ny] : T(0);
-    T acc = w0 * p0;
-    acc += w1 * p1;
-    acc += w2 * p2;
-    acc += w3 * p3;
-    acc += w4 * p4;
-    acc += w5 * p5;
-    s = acc;
-    d = ((((w0 + w1) + w2) + w3) + w4) + w5;
+    s = stencil_sum(w0, w1, w2, w3, w4, w5, p0, p1, p2, p3, p4, p5);
+    d = stencil_diag(w0, w1, w2, w3, w4, w5);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -454,6 +469,281 @@ __global__ void __launch_bounds__(512) k_coarse_solve(const double* __restrict__
         double acc = 0;
         for (int jj = 0; jj < n; jj++) acc += Binv[(size_t)jj * n + t] * rs[jj];
         e[t] = (T)(-acc);
+    }
+}
+
+// Workgroup barrier that only orders LDS traffic: waits for this wave's
+// outstanding LDS operations, not for its global loads, so loads issued for the
+// next plane stay in flight across it.  (Global results are only consumed by
+// the issuing thread, after the compiler's own wait.)
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Map the dispatch order of workgroups onto tiles so that each XCD works on a
+// contiguous range of tiles: workgroup w is dispatched to XCD w % 8, and XCD x
+// receives logical tiles [start_x, start_x + count_x).  Neighbouring tiles then
+// share one L2, where their halo re-reads hit.
+__device__ __forceinline__ int xcd_tile(int w, int nwg) {
+    const int q = nwg >> 3, r = nwg & 7, x = w & 7, m = w >> 3;
+    return x * q + min(x, r) + m;
+}
+
+// One full red-black Gauss-Seidel sweep (colour c0 first, then 1 - c0) in a
+// single pass over HBM, out of place (pin -> pout, so tiles never race).
+//
+// A workgroup owns a TX x TY column of cells and marches upward through a chunk
+// of kc planes.  Planes of pin are staged in LDS with a 2-cell ring; the first
+// colour is updated on the tile plus a 1-cell ring (the ring values are the
+// same ones the neighbouring tile computes, bit for bit), so the second colour
+// can be updated on the tile from LDS alone.  At step t the first colour is
+// updated on plane t and the second colour on plane t-1, which is then final
+// and written out.  Thread (li, lj) owns ring-1 column (li, lj) and keeps that
+// column's face coefficients and right-hand side for two planes in registers.
+// Below plane k0 and above k1-1 the first colour is recomputed redundantly
+// (planes k0-1 and k1) so chunks are independent.  The global loads of plane
+// t+2 (pin) and t+1 (faces, b) are issued before the compute of step t and
+// written to LDS at the start of step t+1.
+template <class T, int TX, int TY>
+__global__ void __launch_bounds__((TX + 2) * (TY + 2)) k_rb_sweep(Lvl<T> L, const T* __restrict__ pin,
+                                                                  T* __restrict__ pout, const T* __restrict__ b,
+                                                                  int c0, int kc, int tiles_x, int tiles_y) {
+    constexpr int W = TX + 4, H = TY + 4, NT = (TX + 2) * (TY + 2), NS = 5;
+    constexpr int NP = (H * W + NT - 1) / NT;  // ring cells loaded per thread
+    __shared__ T sp[NS][H][W];
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, chunk = tile / (tiles_x * tiles_y);
+    const int i0 = tx * TX, j0 = ty * TY;
+    const int k0 = chunk * kc, k1 = min(nz, k0 + kc);
+    const int tid = threadIdx.x;
+    const int li = tid % (TX + 2), lj = tid / (TX + 2);
+    const int gi = i0 + li - 1, gj = j0 + lj - 1;
+    const bool incell = gi >= 0 && gi < nx && gj >= 0 && gj < ny;
+    const bool interior = incell && li >= 1 && li <= TX && lj >= 1 && lj <= TY;
+    const size_t plane = (size_t)nx * ny;
+
+    // the ring cells this thread stages: offsets into a plane (-1 = outside the grid)
+    long roff[NP];
+    int rpos[NP];
+#pragma unroll
+    for (int u = 0; u < NP; u++) {
+        const int q = tid + u * NT;
+        rpos[u] = q < H * W ? q : -1;
+        const int qi = q % W, qj = q / W;
+        const int ii = i0 + qi - 2, jj = j0 + qj - 2;
+        roff[u] = (q < H * W && ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? (long)jj * nx + ii : -1;
+    }
+    T* const spf = &sp[0][0][0];
+    auto slot = [](int k) { return (k + 2 * NS) % NS; };
+    auto fetch_ring = [&](int k, T* v) {
+        const bool kin = k >= 0 && k < nz;
+#pragma unroll
+        for (int u = 0; u < NP; u++) v[u] = (kin && roff[u] >= 0) ? pin[(size_t)k * plane + roff[u]] : T(0);
+    };
+    auto store_ring = [&](int k, const T* v) {
+        T* dst = spf + slot(k) * (H * W);
+#pragma unroll
+        for (int u = 0; u < NP; u++)
+            if (rpos[u] >= 0) dst[rpos[u]] = v[u];
+    };
+    struct FB {
+        T w0, w1, w2, w3, w4, w5, bb;
+    };
+    auto fetch_fb = [&](int k) {
+        FB f{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+        if (incell && k >= 0 && k < nz) {
+            f.w0 = L.bx[fxi(gi, gj, k, nx, ny)];
+            f.w1 = L.bx[fxi(gi + 1, gj, k, nx, ny)];
+            f.w2 = L.by[fyi(gi, gj, k, nx, ny)];
+            f.w3 = L.by[fyi(gi, gj + 1, k, nx, ny)];
+            f.w4 = L.bz[fzi(gi, gj, k, nx, ny)];
+            f.w5 = L.bz[fzi(gi, gj, k + 1, nx, ny)];
+            f.bb = b[(size_t)k * plane + (size_t)gj * nx + gi];
+        }
+        return f;
+    };
+
+    T ring[NP];
+    fetch_ring(k0 - 2, ring);
+    store_ring(k0 - 2, ring);
+    fetch_ring(k0 - 1, ring);
+    store_ring(k0 - 1, ring);
+    fetch_ring(k0, ring);              // plane t+1 for the first step
+    FB fnext = fetch_fb(k0 - 1);       // plane t for the first step
+    FB fcur, fprev = fnext;
+    for (int t = k0 - 1; t <= k1; t++) {
+        store_ring(t + 1, ring);
+        fcur = fnext;
+        lds_barrier();
+        fetch_ring(t + 2, ring);       // in flight during this step
+        fnext = fetch_fb(t + 1);
+        if (incell && t >= 0 && t < nz && (((gi + gj + t) & 1) == c0)) {
+            T(*c)[W] = sp[slot(t)];
+            const T s = stencil_sum(fcur.w0, fcur.w1, fcur.w2, fcur.w3, fcur.w4, fcur.w5, c[lj + 1][li],
+                                    c[lj + 1][li + 2], c[lj][li + 1], c[lj + 2][li + 1],
+                                    sp[slot(t - 1)][lj + 1][li + 1], sp[slot(t + 1)][lj + 1][li + 1]);
+            c[lj + 1][li + 1] = (s - fcur.bb) / stencil_diag(fcur.w0, fcur.w1, fcur.w2, fcur.w3, fcur.w4, fcur.w5);
+        }
+        lds_barrier();
+        const int tp = t - 1;
+        if (interior && tp >= k0 && tp < k1) {
+            T(*c)[W] = sp[slot(tp)];
+            T v;
+            if (((gi + gj + tp) & 1) != c0) {
+                const T s = stencil_sum(fprev.w0, fprev.w1, fprev.w2, fprev.w3, fprev.w4, fprev.w5, c[lj + 1][li],
+                                        c[lj + 1][li + 2], c[lj][li + 1], c[lj + 2][li + 1],
+                                        sp[slot(tp - 1)][lj + 1][li + 1], sp[slot(tp + 1)][lj + 1][li + 1]);
+                v = (s - fprev.bb) / stencil_diag(fprev.w0, fprev.w1, fprev.w2, fprev.w3, fprev.w4, fprev.w5);
+            } else {
+                v = c[lj + 1][li + 1];
+            }
+            pout[(size_t)tp * plane + (size_t)gj * nx + gi] = v;
+        }
+        fprev = fcur;
+    }
+}
+
+// ---------------------------------------------------------------- z-marching residual kernels
+//
+// A workgroup (CBX x CBY threads) owns a tile of columns and marches up a chunk
+// of planes; each thread keeps its column's p at planes k-1, k, k+1 and the
+// z-face below in registers and loads everything of plane k+1 one step ahead,
+// so every array is read from HBM about once (the y-neighbour rows at the tile
+// edge hit L2 when the neighbouring tile runs on the same XCD, see xcd_tile).
+
+constexpr int CBX = 64, CBY = 4;
+
+struct ColGrid {
+    int tiles_x, tiles_y, kc;
+};
+
+// Values of one cell's stencil at one plane: own p, 4 in-plane neighbours,
+// right-hand side and the 5 faces that are not carried from the plane below.
+template <class T>
+struct Plane1 {
+    T p, pw, pe, ps, pn, b, wx0, wx1, wy0, wy1, wz1;
+};
+
+template <class T>
+__device__ __forceinline__ Plane1<T> load_plane1(const Lvl<T>& L, const T* __restrict__ p, const T* __restrict__ b,
+                                                 int i, int j, int k) {
+    Plane1<T> v;
+    const int nx = L.nx, ny = L.ny;
+    const size_t c = cidx(i, j, k, nx, ny);
+    v.p = p[c];
+    v.pw = i > 0 ? p[c - 1] : T(0);
+    v.pe = i < nx - 1 ? p[c + 1] : T(0);
+    v.ps = j > 0 ? p[c - nx] : T(0);
+    v.pn = j < ny - 1 ? p[c + nx] : T(0);
+    v.b = b[c];
+    v.wx0 = L.bx[fxi(i, j, k, nx, ny)];
+    v.wx1 = L.bx[fxi(i + 1, j, k, nx, ny)];
+    v.wy0 = L.by[fyi(i, j, k, nx, ny)];
+    v.wy1 = L.by[fyi(i, j + 1, k, nx, ny)];
+    v.wz1 = L.bz[fzi(i, j, k + 1, nx, ny)];
+    return v;
+}
+
+// Residual r = b - L p along each column; MODE 0: partial sums of r^2 and p;
+// MODE 1 (FP64 refinement): also writes r32 = float(r * inv_s).
+template <class T, int MODE>
+__global__ void __launch_bounds__(CBX* CBY) k_resid_col(Lvl<T> L, const T* __restrict__ p, const T* __restrict__ b,
+                                                       ColGrid G, double inv_s, float* __restrict__ r32,
+                                                       double* __restrict__ part) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
+    const int i = tx * CBX + (int)(threadIdx.x % CBX), j = ty * CBY + (int)(threadIdx.x / CBX);
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int k0 = chunk * G.kc, k1 = min(nz, k0 + G.kc);
+    double a = 0, q = 0;
+    if (i < nx && j < ny && k0 < k1) {
+        const size_t plane = (size_t)nx * ny;
+        const size_t col = (size_t)j * nx + i;
+        T pbelow = k0 > 0 ? p[(size_t)(k0 - 1) * plane + col] : T(0);
+        T wz0 = L.bz[fzi(i, j, k0, nx, ny)];
+        Plane1<T> cur = load_plane1(L, p, b, i, j, k0);
+        Plane1<T> nxt = cur;
+        for (int k = k0; k < k1; k++) {
+            if (k + 1 < nz) nxt = load_plane1(L, p, b, i, j, k + 1);
+            const T pabove = k + 1 < nz ? nxt.p : T(0);
+            const T s = stencil_sum(cur.wx0, cur.wx1, cur.wy0, cur.wy1, wz0, cur.wz1, cur.pw, cur.pe, cur.ps,
+                                    cur.pn, pbelow, pabove);
+            const T d = stencil_diag(cur.wx0, cur.wx1, cur.wy0, cur.wy1, wz0, cur.wz1);
+            const T r = cur.b - (s - d * cur.p);
+            if (MODE == 1) r32[(size_t)k * plane + col] = (float)((double)r * inv_s);
+            a += (double)r * (double)r;
+            q += (double)cur.p;
+            pbelow = cur.p;
+            wz0 = cur.wz1;
+            cur = nxt;
+        }
+    }
+    // deterministic block partials
+    __shared__ double sa[CBX * CBY / 64], sb[CBX * CBY / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        q += __shfl_down(q, off, 64);
+    }
+    if (threadIdx.x % 64 == 0) { sa[threadIdx.x / 64] = a; sb[threadIdx.x / 64] = q; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0, tb = 0;
+        for (int w = 0; w < CBX * CBY / 64; w++) { ta += sa[w]; tb += sb[w]; }
+        part[2 * tile] = ta;
+        part[2 * tile + 1] = tb;
+    }
+}
+
+// Residual restricted to the next level.  A wavefront covers 32 x 2 fine
+// columns (lane l: i = i0 + l % 32, j = j0 + l / 32), so the 2 x 2 children of
+// a coarse column sit in lanes l, l^1, l^32, l^33; each thread marches up its
+// column, sums its residuals over the plane pair 2K, 2K+1, and the four sums are
+// combined with lane shuffles.  rc(I,J,K) = 1/2 * (sum of the 8 child residuals).
+// Tiles are 32 x 8 fine columns (4 wavefronts); kc (planes per chunk) is even.
+constexpr int RBX = 32, RBY = 8;
+
+template <class T>
+__global__ void __launch_bounds__(256) k_resid_restrict_col(Lvl<T> L, const T* __restrict__ p,
+                                                           const T* __restrict__ b, ColGrid G,
+                                                           T* __restrict__ rc) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int cnx = nx / 2, cny = ny / 2;
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int i = tx * RBX + lane % 32, j = ty * RBY + 2 * wave + lane / 32;
+    const int k0 = chunk * G.kc, k1 = min(nz, k0 + G.kc);
+    const bool active = i < nx && j < ny;   // nx, ny even: a 2x2 group is all in or all out
+    const size_t plane = (size_t)nx * ny;
+    const size_t col = (size_t)j * nx + i;
+    T pbelow = T(0), wz0 = T(0);
+    Plane1<T> cur{}, nxt{};
+    if (active && k0 < k1) {
+        pbelow = k0 > 0 ? p[(size_t)(k0 - 1) * plane + col] : T(0);
+        wz0 = L.bz[fzi(i, j, k0, nx, ny)];
+        cur = load_plane1(L, p, b, i, j, k0);
+    }
+    T acc = 0;
+    for (int k = k0; k < k1; k++) {
+        if (active) {
+            if (k + 1 < nz) nxt = load_plane1(L, p, b, i, j, k + 1);
+            const T pabove = k + 1 < nz ? nxt.p : T(0);
+            const T s = stencil_sum(cur.wx0, cur.wx1, cur.wy0, cur.wy1, wz0, cur.wz1, cur.pw, cur.pe, cur.ps, cur.pn,
+                                    pbelow, pabove);
+            const T d = stencil_diag(cur.wx0, cur.wx1, cur.wy0, cur.wy1, wz0, cur.wz1);
+            acc += cur.b - (s - d * cur.p);
+            pbelow = cur.p;
+            wz0 = cur.wz1;
+            cur = nxt;
+        }
+        if (k & 1) {
+            T v = acc;
+            v += __shfl_xor(v, 1, 64);
+            v += __shfl_xor(v, 32, 64);
+            if (active && !(i & 1) && !(j & 1)) rc[cidx(i >> 1, j >> 1, k >> 1, cnx, cny)] = T(0.5) * v;
+            acc = 0;
+        }
     }
 }
 

@@ -21,13 +21,14 @@ MG_BC_NEUMANN = 0
 MG_MAX_LEVELS = 24
 MG_MAX_COARSE_CELLS = 512
 MG_MAX_HISTORY = 256
+MG_NUM_TILES = 8
 KERNEL_CLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "refine", "other", "smooth_fine"]
 MG_K_COUNT = len(KERNEL_CLASSES)
 
 # every function declared in include/mg.h
 EXPORTS = [
     "mg_default_options", "mg_workspace_bytes", "mg_setup", "mg_solve", "mg_destroy",
-    "mg_level_dims", "mg_copy_level", "mg_server_create", "mg_batch_submit", "mg_poll",
+    "mg_level_dims", "mg_level_tile", "mg_copy_level", "mg_server_create", "mg_batch_submit", "mg_poll",
     "mg_server_destroy", "mg_status_string", "mg_last_error",
 ]
 
@@ -39,7 +40,7 @@ class Grid(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
                 ("n_coarsest", ctypes.c_int), ("inner_m", ctypes.c_int),
-                ("max_cycles", ctypes.c_int), ("profile", ctypes.c_int)]
+                ("max_cycles", ctypes.c_int), ("profile", ctypes.c_int), ("tile", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -100,6 +101,7 @@ def lib():
     L.mg_destroy.restype = None
     L.mg_level_dims.argtypes = [vp, i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
     L.mg_copy_level.argtypes = [vp, i, vp, vp, vp, vp, vp]
+    L.mg_level_tile.argtypes = [vp, i, ctypes.POINTER(i)]
     L.mg_server_create.argtypes = [vp, sz, ctypes.POINTER(ServerOptions), ctypes.POINTER(vp)]
     L.mg_batch_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
     L.mg_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Result)]
@@ -125,12 +127,14 @@ class MGError(RuntimeError):
         self.status = status
 
 
-def options(precision="fp64", nu1=2, nu2=2, n_coarsest=4, inner_m=1, max_cycles=100, profile=False):
+def options(precision="fp64", nu1=2, nu2=2, n_coarsest=4, inner_m=1, max_cycles=100, profile=False,
+            tile=0):
     o = Options()
     lib().mg_default_options(ctypes.byref(o))
     o.precision = {"fp64": MG_FP64, "fp32_refined": MG_FP32_REFINED}[precision]
     o.nu1, o.nu2, o.n_coarsest, o.inner_m, o.max_cycles = nu1, nu2, n_coarsest, inner_m, max_cycles
     o.profile = 1 if profile else 0
+    o.tile = tile
     return o
 
 
@@ -210,6 +214,14 @@ class Solver:
             if lib().mg_level_dims(self.h, l, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)) != MG_OK:
                 break
             out.append((a.value, b.value, c.value))
+        return out
+
+    def tiles(self):
+        out = []
+        for l in range(len(self.levels())):
+            t = ctypes.c_int()
+            lib().mg_level_tile(self.h, l, ctypes.byref(t))
+            out.append(t.value)
         return out
 
     def level_arrays(self, l):
