@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ["paper_1410_8568_amd/csrc/mg_kernels.h"]
 METRIC = "time to 1e-10 residual + HBM GB/s per V-cycle; FP32-refined vs FP64 MG"
 
 
@@ -69,18 +71,92 @@ def cpu_baseline(P, n_coarsest, outer_needed, precision):
     import oracle
     oracle.lib()
     t0 = time.perf_counter()
-    r = oracle.solve(P.bx, P.by, P.bz, P.b, n_coarsest=n_coarsest, max_cycles=1, tol=1e-10,
+    its = 4
+    r = oracle.solve(P.bx, P.by, P.bz, P.b, n_coarsest=n_coarsest, max_cycles=its, tol=1e-10,
                      precision=precision)
     wall = time.perf_counter() - t0
     setup_s, rest_s = oracle.last_timing()
-    # rest_s = projection + initial residual + 1 iteration (+ residual); scale the
-    # iteration part by the GPU's count
-    est_s = setup_s + rest_s * outer_needed
+    # rest_s = projection + initial residual + `its` iterations with their residuals;
+    # scale the per-iteration time by the GPU's count (the solve step excludes setup)
+    per_it = rest_s / its
+    est_s = per_it * outer_needed
     return dict(value=est_s * 1e3, unit="ms", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{precision} oracle on the same {P.n[0]}^3 input: hierarchy setup "
-                       f"({setup_s:.2f} s) + one outer iteration with its residual "
-                       f"({rest_s:.2f} s), scaled to {outer_needed} iterations; "
+                sample=f"{precision} oracle on the same {P.n[0]}^3 input: {its} outer iterations "
+                       f"({rest_s:.2f} s, after {setup_s:.2f} s of hierarchy setup), per-iteration time "
+                       f"scaled to the {outer_needed} iterations the GPU solve took; "
                        f"{wall:.1f} s of CPU wall time measured")
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None
+    if there is none or the kernel sources changed since it was taken."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except Exception:
+        return None
+    if t.get("source_sha") != kernel_source_sha() or t.get("class") != kernel:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def calibrate_copy(gib=1, reps=5):
+    """A plain device copy of known size, for scaling the FETCH_SIZE/WRITE_SIZE counters."""
+    import torch
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes_read": 4 * n, "calibrate_copy_bytes_written": 4 * n, "reps": reps}))
+
+
+def summarize(d):
+    """Markdown summary of rocprofv3 CSV output in directory d (kernel stats,
+    per-dispatch durations by grid size, counters per dispatch)."""
+    import csv
+    import glob
+    import statistics
+    out = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+        rows = list(csv.DictReader(open(f)))
+        out.append(f"### kernel stats ({os.path.basename(f)})\n")
+        out.append("| kernel | calls | total ms | avg us | % |\n|---|---|---|---|---|")
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:20]:
+            out.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['TotalDurationNs'])/1e6:.3f} | "
+                       f"{float(r['AverageNs'])/1e3:.2f} | {float(r['Percentage']):.1f} |")
+        out.append("")
+    for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)):
+        rows = list(csv.DictReader(open(f)))
+        groups = {}
+        for r in rows:
+            key = (r["Kernel_Name"][:90], r.get("Grid_Size", r.get("Grid_Size_X", "?")))
+            groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        out.append(f"### dispatches by kernel and grid size ({os.path.basename(f)})\n")
+        out.append("| kernel | grid | calls | avg us | median us |\n|---|---|---|---|---|")
+        for (k, g), v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:25]:
+            out.append(f"| {k} | {g} | {len(v)} | {statistics.mean(v):.2f} | {statistics.median(v):.2f} |")
+        out.append("")
+    for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        rows = list(csv.DictReader(open(f)))
+        groups = {}
+        for r in rows:
+            key = (r["Kernel_Name"][:90], r["Grid_Size"], r["Counter_Name"])
+            groups.setdefault(key, []).append(float(r["Counter_Value"]))
+        out.append(f"### counters per dispatch ({os.path.basename(f)})\n")
+        out.append("| kernel | grid | counter | dispatches | avg KiB |\n|---|---|---|---|---|")
+        for (k, g, c), v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:25]:
+            out.append(f"| {k} | {g} | {c} | {len(v)} | {statistics.mean(v):.1f} |")
+        out.append("")
+    print("\n".join(out))
 
 
 def main():
@@ -93,10 +169,19 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (counter scale)")
+    ap.add_argument("--summarize", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize)
+        return
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(independent problems shard across GPUs without communication, see the design notes)",
+              f"(independent problems shard across GPUs without communication; one large solve "
+              f"would need a halo-exchange domain decomposition, which is not built)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -184,7 +269,7 @@ def main():
         "gbps_per_vcycle": bytes32 / cyc32 / 1e6 / (ms32 / cyc32),
         "cell_updates_per_s": N * cyc32 / (ms32 * 1e-3),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_for(dom),
                      "avg_launch_ms": dom_avg_ms, "bytes_per_launch": dom_bytes},
         "kernel_ms_fp32_refined": prof32["kernel_ms"],
     }
