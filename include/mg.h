@@ -86,7 +86,7 @@ typedef struct {
                         ping-pong buffer.  Every choice gives bit-identical results. */
 } mg_options;
 
-/* Fused sweep variants: tile (cells) 64x4, 64x8, 64x12, 32x8, each with a
+/* Fused sweep variants: tile (cells) 64x8, 128x4, 128x8, 64x16, each with a
    target of about 1024 (odd) or 4096 (even) workgroups: variant v uses tile
    (v-1)/2 and target (v-1)%2. */
 #define MG_NUM_TILES 8

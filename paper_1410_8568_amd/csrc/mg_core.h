@@ -102,6 +102,7 @@ struct SolveState {
     double norm_b = 0, rho0 = 0, rho = 0, scale = 1;
     int it = 0;
     int status = MG_OK;
+    bool project = false;  // p still needs its final mean-zero projection
     std::chrono::steady_clock::time_point t0;
 };
 mg_status solve_begin(SolveState& S);             // blocking: projection + initial residual

@@ -138,9 +138,9 @@ mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
     const bool f32 = o->precision == MG_FP32_REFINED;
     for (int l = 0; l < L->nlev; l++) {
         const LevelDims& ld = L->d[l];
-        L->bx[l] = take(ld.nfx() * 8);
-        L->by[l] = take(ld.nfy() * 8);
-        L->bz[l] = take(ld.nfz() * 8);
+        L->bx[l] = take(ld.ncell() * 8);
+        L->by[l] = take(ld.ncell() * 8);
+        L->bz[l] = take(ld.ncell() * 8);
         L->a[l] = take(ld.ncell() * 8);
         if (l > 0 && !f32) {
             L->e[l] = take(ld.ncell() * 8);
@@ -148,9 +148,9 @@ mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
         }
         if (!f32 && l < L->nlev - 1) L->tmp[l] = take(ld.ncell() * 8);
         if (f32) {
-            L->fbx[l] = take(ld.nfx() * 4);
-            L->fby[l] = take(ld.nfy() * 4);
-            L->fbz[l] = take(ld.nfz() * 4);
+            L->fbx[l] = take(ld.ncell() * 4);
+            L->fby[l] = take(ld.ncell() * 4);
+            L->fbz[l] = take(ld.ncell() * 4);
             L->fa[l] = take(ld.ncell() * 4);
             L->fe[l] = take(ld.ncell() * 4);
             L->frhs[l] = take(ld.ncell() * 4);
@@ -261,32 +261,31 @@ mg_status setup_impl(mg_handle* h, const double* bx, const double* by, const dou
     hipStream_t s = h->stream;
     HIPCHK(hipMemsetAsync(h->flag, 0, 64, s));
     const LevelDims& d0 = L.d[0];
-    k_copy_faces<<<lin_grid(d0.nfx()), 256, 0, s>>>(bx, h->bx[0], d0.nx + 1, d0.ny, d0.nz, 0, h->flag);
-    k_copy_faces<<<lin_grid(d0.nfy()), 256, 0, s>>>(by, h->by[0], d0.nx, d0.ny + 1, d0.nz, 1, h->flag);
-    k_copy_faces<<<lin_grid(d0.nfz()), 256, 0, s>>>(bz, h->bz[0], d0.nx, d0.ny, d0.nz + 1, 2, h->flag);
+    k_faces_from_api<<<lin_grid(d0.ncell()), 256, 0, s>>>(bx, by, bz, h->bx[0], h->by[0], h->bz[0], d0.nx, d0.ny,
+                                                          d0.nz, h->flag);
     HIPCHK(hipGetLastError());
     for (int l = 0; l < L.nlev; l++) {
         const LevelDims& d = L.d[l];
         if (l > 0) {
             const LevelDims& f = L.d[l - 1];
-            k_coarsen_x<<<lin_grid(d.nfx()), 256, 0, s>>>(h->bx[l - 1], h->bx[l], f.nx, f.ny, d.nx, d.ny, d.nz);
-            k_coarsen_y<<<lin_grid(d.nfy()), 256, 0, s>>>(h->by[l - 1], h->by[l], f.nx, f.ny, d.nx, d.ny, d.nz);
-            k_coarsen_z<<<lin_grid(d.nfz()), 256, 0, s>>>(h->bz[l - 1], h->bz[l], f.nx, f.ny, d.nx, d.ny, d.nz);
+            k_coarsen<<<lin_grid(d.ncell()), 256, 0, s>>>(h->bx[l - 1], h->by[l - 1], h->bz[l - 1], h->bx[l], h->by[l],
+                                                          h->bz[l], f.nx, f.ny, d.nx, d.ny, d.nz);
         }
-        k_cell_weights<<<lin_grid(d.ncell()), 256, 0, s>>>(h->bx[l], h->by[l], h->bz[l], h->a[l], d.nx, d.ny,
-                                                           d.nz);
+        k_cell_weights<<<lin_grid(d.ncell()), 256, 0, s>>>(Lvl<double>{d.nx, d.ny, d.nz, h->bx[l], h->by[l], h->bz[l]},
+                                                           h->a[l]);
     }
     HIPCHK(hipGetLastError());
     const LevelDims& c = L.d[L.nlev - 1];
-    k_coarse_invert<<<1, FIN_THREADS, 0, s>>>(h->bx[L.nlev - 1], h->by[L.nlev - 1], h->bz[L.nlev - 1], c.nx,
-                                              c.ny, c.nz, h->binv, h->flag + 1);
+    const int lc = L.nlev - 1;
+    k_coarse_invert<<<1, FIN_THREADS, 0, s>>>(Lvl<double>{c.nx, c.ny, c.nz, h->bx[lc], h->by[lc], h->bz[lc]}, h->binv,
+                                              h->flag + 1);
     HIPCHK(hipGetLastError());
     if (h->o.precision == MG_FP32_REFINED) {
         for (int l = 0; l < L.nlev; l++) {
             const LevelDims& d = L.d[l];
-            k_cast_d2f<<<lin_grid(d.nfx()), 256, 0, s>>>(h->bx[l], h->fbx[l], d.nfx());
-            k_cast_d2f<<<lin_grid(d.nfy()), 256, 0, s>>>(h->by[l], h->fby[l], d.nfy());
-            k_cast_d2f<<<lin_grid(d.nfz()), 256, 0, s>>>(h->bz[l], h->fbz[l], d.nfz());
+            k_cast_d2f<<<lin_grid(d.ncell()), 256, 0, s>>>(h->bx[l], h->fbx[l], d.ncell());
+            k_cast_d2f<<<lin_grid(d.ncell()), 256, 0, s>>>(h->by[l], h->fby[l], d.ncell());
+            k_cast_d2f<<<lin_grid(d.ncell()), 256, 0, s>>>(h->bz[l], h->fbz[l], d.ncell());
             k_cast_d2f<<<lin_grid(d.ncell()), 256, 0, s>>>(h->a[l], h->fa[l], d.ncell());
         }
         HIPCHK(hipGetLastError());
@@ -339,25 +338,28 @@ struct Hier {
 };
 
 template <class T, int TX, int TY>
-static void launch_sweep(hipStream_t s, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0, int target) {
+static void launch_sweep(hipStream_t s, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0, int target,
+                         const double* shift_sum) {
     const int gx = (L.nx + TX - 1) / TX, gy = (L.ny + TY - 1) / TY;
     const int tiles = gx * gy;
     // chunks of >= 8 planes, so the redundant planes at chunk ends stay a small fraction
     int chunks = std::max(1, std::min(std::max(1, L.nz / 8), (target + tiles - 1) / tiles));
     const int kc = (L.nz + chunks - 1) / chunks;
     chunks = (L.nz + kc - 1) / kc;
-    k_rb_sweep<T, TX, TY><<<dim3(tiles * chunks), (TX + 2) * (TY + 2), 0, s>>>(L, pin, pout, b, c0, kc, gx, gy);
+    k_rb_sweep<T, TX, TY><<<dim3(tiles * chunks), (TX / 2 + 2) * (TY + 2), 0, s>>>(
+        L, pin, pout, b, c0, kc, gx, gy, shift_sum, (double)L.nx * L.ny * L.nz);
 }
 
 // Fused sweep variant v in 1..MG_NUM_TILES.
 template <class T>
-static void fused_sweep(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0) {
+static void fused_sweep(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0,
+                        const double* shift_sum = nullptr) {
     const int target = ((v - 1) & 1) ? 4096 : 1024;
     switch ((v - 1) >> 1) {
-        case 0: launch_sweep<T, 64, 4>(s, L, pin, pout, b, c0, target); break;
-        case 1: launch_sweep<T, 64, 8>(s, L, pin, pout, b, c0, target); break;
-        case 2: launch_sweep<T, 64, 12>(s, L, pin, pout, b, c0, target); break;
-        default: launch_sweep<T, 32, 8>(s, L, pin, pout, b, c0, target); break;
+        case 0: launch_sweep<T, 64, 8>(s, L, pin, pout, b, c0, target, shift_sum); break;
+        case 1: launch_sweep<T, 128, 4>(s, L, pin, pout, b, c0, target, shift_sum); break;
+        case 2: launch_sweep<T, 128, 8>(s, L, pin, pout, b, c0, target, shift_sum); break;
+        default: launch_sweep<T, 64, 16>(s, L, pin, pout, b, c0, target, shift_sum); break;
     }
 }
 
@@ -464,36 +466,46 @@ static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b
     return MG_OK;
 }
 
-// nsweep red-black sweeps on level l, first colour c0 (0: red first).
+// nsweep red-black sweeps on level l, first colour c0 (0: red first): pairs of
+// fused out-of-place sweeps (ping-pong through tmp), then one in-place sweep of
+// the reference kernels if nsweep is odd or the level uses them throughout.
+// shift_sum (optional): the first fused sweep subtracts shift_sum[0]/N from the
+// iterate as it reads it; returns false if there was no fused sweep to do so.
 template <class T>
-static void smooth(mg_handle* h, Hier<T>& H, int l, int nsweep, int c0) {
-    if (nsweep <= 0) return;
+static bool smooth(mg_handle* h, Hier<T>& H, int l, int nsweep, int c0, const double* shift_sum = nullptr) {
+    if (nsweep <= 0) return shift_sum == nullptr;
     hipStream_t s = h->stream;
     const LevelDims& d = H.d[l];
     const int cls = l == 0 ? MG_K_SMOOTH_FINE : MG_K_SMOOTH;
     const double full = (3.0 * d.ncell() + d.nfaces()) * sizeof(T);
     const int tile = H.tmp[l] ? h->tile[l] : -1;
+    bool shifted = shift_sum == nullptr;
     int rem = nsweep;
-    if (tile < 0 || (rem & 1)) {
-        const int n_ref = tile < 0 ? rem : 1;
-        for (int it = 0; it < n_ref; it++) {
+    if (tile > 0) {
+        for (; rem >= 2; rem -= 2) {
+            {
+                Prof pf(h, cls, full);
+                fused_sweep<T>(s, tile, H.L[l], H.e[l], H.tmp[l], H.rhs[l], c0, shifted ? nullptr : shift_sum);
+                shifted = true;
+            }
             Prof pf(h, cls, full);
-            ref_sweep<T>(s, H.L[l], H.e[l], H.rhs[l], c0);
+            fused_sweep<T>(s, tile, H.L[l], H.tmp[l], H.e[l], H.rhs[l], c0);
         }
-        rem -= n_ref;
     }
-    for (; rem >= 2; rem -= 2) {
-        {
-            Prof pf(h, cls, full);
-            fused_sweep<T>(s, tile, H.L[l], H.e[l], H.tmp[l], H.rhs[l], c0);
-        }
+    for (; rem > 0; rem--) {
         Prof pf(h, cls, full);
-        fused_sweep<T>(s, tile, H.L[l], H.tmp[l], H.e[l], H.rhs[l], c0);
+        ref_sweep<T>(s, H.L[l], H.e[l], H.rhs[l], c0);
     }
+    return shifted;
+}
+
+// True when the first pre-smoothing pass on level 0 can absorb the mean shift.
+static bool fused_first_sweep(const mg_handle* h) {
+    return h->L.nlev > 1 && h->tile[0] > 0 && h->o.nu1 >= 2;
 }
 
 template <class T>
-static void vcycle(mg_handle* h, Hier<T>& H, int l) {
+static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nullptr) {
     hipStream_t s = h->stream;
     const LevelDims& d = H.d[l];
     if (l == H.nlev - 1) {
@@ -501,8 +513,7 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l) {
         k_coarse_solve<T><<<1, 512, 0, s>>>(h->binv, h->L.ncoarse, H.rhs[l], H.e[l]);
         return;
     }
-    const dim3 g = col_grid(d.nx, d.ny, d.nz), blk(BX, BY);
-    smooth(h, H, l, h->o.nu1, 0);
+    smooth(h, H, l, h->o.nu1, 0, shift_sum);
     const LevelDims& c = H.d[l + 1];
     {
         Prof pf(h, MG_K_RESTRICT, ((2.0 * d.ncell() + d.nfaces()) + c.ncell()) * sizeof(T));
@@ -517,7 +528,9 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l) {
     vcycle(h, H, l + 1);
     {
         Prof pf(h, MG_K_PROLONG, (2.0 * d.ncell() + 2.0 * c.ncell()) * sizeof(T));
-        k_prolong_add<T><<<g, blk, 0, s>>>(H.e[l + 1], H.a[l + 1], c.nx, c.ny, c.nz, H.e[l]);
+        int nbp = 0;
+        const ColGrid G = zgrid(d.nx, d.ny, d.nz, false, &nbp);
+        k_prolong_col<T><<<nbp, CBX * CBY, 0, s>>>(H.e[l + 1], H.a[l + 1], c.nx, c.ny, c.nz, G, H.e[l]);
     }
     smooth(h, H, l, h->o.nu2, 1);
 }
@@ -606,10 +619,7 @@ mg_status solve_begin(SolveState& S) {
         k_resid_col<double, 0><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, 1.0, nullptr, h->part);
     }
     finish(h, nbz, 4);
-    {
-        Prof pf(h, MG_K_OTHER, 16.0 * N);
-        k_sub_mean<double><<<g0, blk, 0, s>>>(S.p, h->scal + 5, d0.nx, d0.ny, d0.nz);
-    }
+    S.project = true;  // scal[5] now holds sum(p); p is made mean-zero lazily
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(h->host, h->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -622,15 +632,17 @@ mg_status solve_begin(SolveState& S) {
 }
 
 // Step 2 (asynchronous): one V-cycle (FP64) or one outer refinement iteration,
-// the new residual norm, the mean-zero projection of p, and the copy of the two
-// scalars to h->host.  The caller synchronises h->stream before solve_after_sync.
+// the new residual norm and sum(p), and the copy of both to h->host.  The
+// mean-zero projection of p after each iteration is folded into the next pass
+// that rewrites p (the first fused pre-smoothing sweep, or the refinement
+// update) and, after the last iteration, done by solve_end.  The caller
+// synchronises h->stream before solve_after_sync.
 mg_status solve_launch_iteration(SolveState& S) {
     mg_handle* h = S.h;
     const LevelDims& d0 = h->L.d[0];
     const double N = (double)d0.ncell();
     hipStream_t s = h->stream;
     const dim3 g0 = col_grid(d0.nx, d0.ny, d0.nz), blk(BX, BY);
-    const int nb0 = (int)(g0.x * g0.y * g0.z);
     const bool f32 = h->o.precision == MG_FP32_REFINED;
     const double resid_bytes = (2.0 * N + d0.nfaces()) * 8.0;
     Lvl<double> L64{d0.nx, d0.ny, d0.nz, h->bx[0], h->by[0], h->bz[0]};
@@ -640,7 +652,13 @@ mg_status solve_launch_iteration(SolveState& S) {
     int nbz = 0;
     const ColGrid G0 = zgrid(d0.nx, d0.ny, d0.nz, false, &nbz);
     if (!f32) {
-        vcycle(h, H64, 0);
+        const double* shift = h->scal + 5;
+        if (!fused_first_sweep(h)) {
+            Prof pf(h, MG_K_OTHER, 16.0 * N);
+            k_sub_mean<double><<<g0, blk, 0, s>>>(S.p, h->scal + 5, d0.nx, d0.ny, d0.nz);
+            shift = nullptr;
+        }
+        vcycle(h, H64, 0, shift);
         S.st.cycles++;
         Prof pf(h, MG_K_NORM, resid_bytes);
         k_resid_col<double, 0><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, 1.0, nullptr, h->part);
@@ -655,12 +673,7 @@ mg_status solve_launch_iteration(SolveState& S) {
         }
         {
             Prof pf(h, MG_K_REFINE, 20.0 * N);
-            k_refine_update<<<g0, blk, 0, s>>>(S.p, h->fe[0], S.scale, d0.nx, d0.ny, d0.nz, h->part);
-        }
-        finish(h, nb0, 6);
-        {
-            Prof pf(h, MG_K_OTHER, 16.0 * N);
-            k_sub_mean<double><<<g0, blk, 0, s>>>(S.p, h->scal + 6, d0.nx, d0.ny, d0.nz);
+            k_refine_update<<<lin_grid(d0.ncell()), 256, 0, s>>>(S.p, h->fe[0], S.scale, d0.ncell(), h->scal + 5);
         }
         // r32 of the next iteration is scaled by a power of two near the RMS of the
         // residual just used (any power of two leaves the FP32 arithmetic unchanged)
@@ -669,10 +682,6 @@ mg_status solve_launch_iteration(SolveState& S) {
         k_resid_col<double, 1><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, 1.0 / S.scale, h->frhs[0], h->part);
     }
     finish(h, nbz, 4);
-    if (!f32) {
-        Prof pf(h, MG_K_OTHER, 16.0 * N);
-        k_sub_mean<double><<<g0, blk, 0, s>>>(S.p, h->scal + 5, d0.nx, d0.ny, d0.nz);
-    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(h->host, h->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     return MG_OK;
@@ -695,9 +704,18 @@ bool solve_running(const SolveState& S) {
     return S.status == MG_E_NOT_CONVERGED && S.it < S.h->o.max_cycles;
 }
 
-// Step 4: statistics.
+// Step 4: final mean-zero projection of p (sum(p) from the last residual pass),
+// then statistics.  Blocking.
 void solve_end(SolveState& S, mg_stats* st) {
     mg_handle* h = S.h;
+    if (S.project) {
+        const LevelDims& d0 = h->L.d[0];
+        Prof pf(h, MG_K_OTHER, 16.0 * d0.ncell());
+        k_sub_mean<double><<<col_grid(d0.nx, d0.ny, d0.nz), dim3(BX, BY), 0, h->stream>>>(S.p, h->scal + 5, d0.nx,
+                                                                                        d0.ny, d0.nz);
+        S.project = false;
+    }
+    (void)hipStreamSynchronize(h->stream);
     S.st.outer = S.it;
     if (h->o.precision == MG_FP64) S.st.cycles = S.it;
     S.st.rel_residual = S.rho;
@@ -863,9 +881,11 @@ mg_status mg_copy_level(const mg_handle* h, int l, double* bx, double* by, doubl
     }
     hipStream_t s = (hipStream_t)stream;
     const LevelDims& d = h->L.d[l];
-    if (bx) HIPCHK(hipMemcpyAsync(bx, h->bx[l], d.nfx() * 8, hipMemcpyDeviceToDevice, s));
-    if (by) HIPCHK(hipMemcpyAsync(by, h->by[l], d.nfy() * 8, hipMemcpyDeviceToDevice, s));
-    if (bz) HIPCHK(hipMemcpyAsync(bz, h->bz[l], d.nfz() * 8, hipMemcpyDeviceToDevice, s));
+    if (bx || by || bz) {
+        k_faces_to_api<<<lin_grid(d.nfx() + d.nfy() + d.nfz()), 256, 0, s>>>(h->bx[l], h->by[l], h->bz[l], bx, by, bz,
+                                                                             d.nx, d.ny, d.nz);
+        HIPCHK(hipGetLastError());
+    }
     if (a) HIPCHK(hipMemcpyAsync(a, h->a[l], d.ncell() * 8, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     return MG_OK;

@@ -1,10 +1,13 @@
 // Device kernels of the multigrid pressure solve (gfx950).
 //
 // Every kernel here is bandwidth-bound stencil or transfer work; none is a dense
-// contraction, so none uses MFMA.  Arrays are [k][j][i] with i fastest; x-faces
-// [nz][ny][nx+1], y-faces [nz][ny+1][nx], z-faces [nz+1][ny][nx]; wall faces are
-// stored as 0, so the stencil needs no boundary branches on the coefficients
-// (out-of-grid neighbour values are read as 0 instead).
+// contraction, so none uses MFMA.  Every device array of a level is [k][j][i]
+// with i fastest and n_x n_y n_z entries, so all arrays share one index c and
+// every row starts on the same alignment.  The face coefficients are stored as
+// "lower face of each cell": fx[c] is the x-face between cells i-1 and i, fy[c]
+// the y-face between rows j-1 and j, fz[c] the z-face between planes k-1 and k;
+// the lower wall faces hold 0 and the upper wall faces are not stored (reads of
+// them are guarded and give 0).  Out-of-grid neighbour values read as 0.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -19,23 +22,26 @@ constexpr int FIN_THREADS = 1024;
 __device__ __forceinline__ size_t cidx(int i, int j, int k, int nx, int ny) {
     return ((size_t)k * ny + j) * nx + i;
 }
-__device__ __forceinline__ size_t fxi(int i, int j, int k, int nx, int ny) {
-    return ((size_t)k * ny + j) * (nx + 1) + i;
-}
-__device__ __forceinline__ size_t fyi(int i, int j, int k, int nx, int ny) {
-    return ((size_t)k * (ny + 1) + j) * nx + i;
-}
-__device__ __forceinline__ size_t fzi(int i, int j, int k, int nx, int ny) {
-    return ((size_t)k * ny + j) * nx + i;
-}
-
 template <class T>
 struct Lvl {
     int nx, ny, nz;
-    const T* bx;
-    const T* by;
-    const T* bz;
+    const T* fx;  // lower x-face of each cell
+    const T* fy;  // lower y-face
+    const T* fz;  // lower z-face
 };
+
+// The six face coefficients of cell (i,j,k) at index c, in the order x-, x+,
+// y-, y+, z-, z+ (upper wall faces are 0).
+template <class T>
+__device__ __forceinline__ void faces6(const Lvl<T>& L, int i, int j, int k, size_t c, T& w0, T& w1, T& w2, T& w3,
+                                       T& w4, T& w5) {
+    w0 = L.fx[c];
+    w1 = i < L.nx - 1 ? L.fx[c + 1] : T(0);
+    w2 = L.fy[c];
+    w3 = j < L.ny - 1 ? L.fy[c + L.nx] : T(0);
+    w4 = L.fz[c];
+    w5 = k < L.nz - 1 ? L.fz[c + (size_t)L.nx * L.ny] : T(0);
+}
 
 // Gauss-Seidel update value and the neighbour sum of eq. (10) from the six face
 // coefficients and neighbour values, faces in the order x-, x+, y-, y+, z-, z+.
@@ -65,9 +71,8 @@ __device__ __forceinline__ void nbsum(const Lvl<T>& L, const T* __restrict__ p, 
                                       T& s, T& d) {
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const size_t c = cidx(i, j, k, nx, ny);
-    T w0 = L.bx[fxi(i, j, k, nx, ny)], w1 = L.bx[fxi(i + 1, j, k, nx, ny)];
-    T w2 = L.by[fyi(i, j, k, nx, ny)], w3 = L.by[fyi(i, j + 1, k, nx, ny)];
-    T w4 = L.bz[fzi(i, j, k, nx, ny)], w5 = L.bz[fzi(i, j, k + 1, nx, ny)];
+    T w0, w1, w2, w3, w4, w5;
+    faces6(L, i, j, k, c, w0, w1, w2, w3, w4, w5);
     T p0 = i > 0 ? p[c - 1] : T(0);
     T p1 = i < nx - 1 ? p[c + 1] : T(0);
     T p2 = j > 0 ? p[c - nx] : T(0);
@@ -194,92 +199,102 @@ __global__ void k_cast_d2f(const double* __restrict__ x, float* __restrict__ y, 
 
 // ---------------------------------------------------------------- setup
 
-// Copy caller faces with walls forced to 0; count non-finite or non-positive
-// interior coefficients into *bad.
-__global__ void k_copy_faces(const double* __restrict__ src, double* __restrict__ dst, int n0, int n1,
-                             int n2, int axis, int* __restrict__ bad) {
-    // array dims [n2][n1][n0]; the face index along `axis` (0: n0, 1: n1, 2: n2) is a wall
-    // at 0 and at its extent - 1
-    size_t total = (size_t)n0 * n1 * n2;
+// Caller faces (x: [nz][ny][nx+1], y: [nz][ny+1][nx], z: [nz+1][ny][nx]) to
+// the lower-face layout, lower wall faces forced to 0; counts non-finite or
+// non-positive interior coefficients into *bad.
+__global__ void k_faces_from_api(const double* __restrict__ sx, const double* __restrict__ sy,
+                                 const double* __restrict__ sz, double* __restrict__ fx, double* __restrict__ fy,
+                                 double* __restrict__ fz, int nx, int ny, int nz, int* __restrict__ bad) {
+    const size_t total = (size_t)nx * ny * nz;
     int nbad = 0;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (size_t)gridDim.x * blockDim.x) {
-        int i0 = (int)(t % n0);
-        size_t r = t / n0;
-        int i1 = (int)(r % n1);
-        int i2 = (int)(r / n1);
-        int f = axis == 0 ? i0 : (axis == 1 ? i1 : i2);
-        int ext = axis == 0 ? n0 : (axis == 1 ? n1 : n2);
-        double v = 0.0;
-        if (f > 0 && f < ext - 1) {
-            v = src[t];
-            if (!(v > 0.0) || !(v < 1e300)) nbad++;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % nx);
+        const size_t r = t / nx;
+        const int j = (int)(r % ny), k = (int)(r / ny);
+        double vx = 0.0, vy = 0.0, vz = 0.0;
+        if (i > 0) {
+            vx = sx[((size_t)k * ny + j) * (nx + 1) + i];
+            if (!(vx > 0.0) || !(vx < 1e300)) nbad++;
         }
-        dst[t] = v;
+        if (j > 0) {
+            vy = sy[((size_t)k * (ny + 1) + j) * nx + i];
+            if (!(vy > 0.0) || !(vy < 1e300)) nbad++;
+        }
+        if (k > 0) {
+            vz = sz[((size_t)k * ny + j) * nx + i];
+            if (!(vz > 0.0) || !(vz < 1e300)) nbad++;
+        }
+        fx[t] = vx;
+        fy[t] = vy;
+        fz[t] = vz;
     }
     if (nbad) atomicAdd(bad, nbad);
 }
 
-// Coarse faces = mean of the 2 x 2 fine faces they cover, ((f00+f10)+(f01+f11))/4.
-__global__ void k_coarsen_x(const double* __restrict__ f, double* __restrict__ c, int fnx, int fny, int cnx,
-                            int cny, int cnz) {
-    size_t total = (size_t)(cnx + 1) * cny * cnz;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+// Lower-face layout back to the caller layout (walls 0), for inspection.
+__global__ void k_faces_to_api(const double* __restrict__ fx, const double* __restrict__ fy,
+                               const double* __restrict__ fz, double* __restrict__ sx, double* __restrict__ sy,
+                               double* __restrict__ sz, int nx, int ny, int nz) {
+    const size_t tx = (size_t)(nx + 1) * ny * nz, ty = (size_t)nx * (ny + 1) * nz, tz = (size_t)nx * ny * (nz + 1);
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tx + ty + tz;
          t += (size_t)gridDim.x * blockDim.x) {
-        int I = (int)(t % (cnx + 1));
-        size_t r = t / (cnx + 1);
-        int J = (int)(r % cny), K = (int)(r / cny);
-        double s0 = f[fxi(2 * I, 2 * J, 2 * K, fnx, fny)] + f[fxi(2 * I, 2 * J + 1, 2 * K, fnx, fny)];
-        double s1 = f[fxi(2 * I, 2 * J, 2 * K + 1, fnx, fny)] + f[fxi(2 * I, 2 * J + 1, 2 * K + 1, fnx, fny)];
-        c[t] = 0.25 * (s0 + s1);
+        if (t < tx) {
+            const int i = (int)(t % (nx + 1));
+            const size_t r = t / (nx + 1);
+            if (sx) sx[t] = i < nx ? fx[r * nx + i] : 0.0;
+        } else if (t < tx + ty) {
+            const size_t u = t - tx;
+            const int i = (int)(u % nx);
+            const size_t r = u / nx;
+            const int j = (int)(r % (ny + 1)), k = (int)(r / (ny + 1));
+            if (sy) sy[u] = j < ny ? fy[((size_t)k * ny + j) * nx + i] : 0.0;
+        } else {
+            const size_t u = t - tx - ty;
+            const size_t plane = (size_t)nx * ny;
+            const size_t k = u / plane;
+            if (sz) sz[u] = k < (size_t)nz ? fz[u] : 0.0;
+        }
     }
 }
 
-__global__ void k_coarsen_y(const double* __restrict__ f, double* __restrict__ c, int fnx, int fny, int cnx,
-                            int cny, int cnz) {
-    size_t total = (size_t)cnx * (cny + 1) * cnz;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (size_t)gridDim.x * blockDim.x) {
-        int I = (int)(t % cnx);
-        size_t r = t / cnx;
-        int J = (int)(r % (cny + 1)), K = (int)(r / (cny + 1));
-        double s0 = f[fyi(2 * I, 2 * J, 2 * K, fnx, fny)] + f[fyi(2 * I + 1, 2 * J, 2 * K, fnx, fny)];
-        double s1 = f[fyi(2 * I, 2 * J, 2 * K + 1, fnx, fny)] + f[fyi(2 * I + 1, 2 * J, 2 * K + 1, fnx, fny)];
-        c[t] = 0.25 * (s0 + s1);
-    }
-}
-
-__global__ void k_coarsen_z(const double* __restrict__ f, double* __restrict__ c, int fnx, int fny, int cnx,
-                            int cny, int cnz) {
-    size_t total = (size_t)cnx * cny * (cnz + 1);
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (size_t)gridDim.x * blockDim.x) {
-        int I = (int)(t % cnx);
-        size_t r = t / cnx;
-        int J = (int)(r % cny), K = (int)(r / cny);
-        double s0 = f[fzi(2 * I, 2 * J, 2 * K, fnx, fny)] + f[fzi(2 * I + 1, 2 * J, 2 * K, fnx, fny)];
-        double s1 = f[fzi(2 * I, 2 * J + 1, 2 * K, fnx, fny)] + f[fzi(2 * I + 1, 2 * J + 1, 2 * K, fnx, fny)];
-        c[t] = 0.25 * (s0 + s1);
+// Coarse faces = mean of the 2 x 2 fine faces of the same orientation that the
+// coarse face covers, ((f00 + f10) + (f01 + f11)) / 4, the first index along the
+// first tangential axis.  One thread per coarse cell computes its three lower
+// faces (the lower wall faces come out 0 from the fine wall faces).
+__global__ void k_coarsen(const double* __restrict__ fx, const double* __restrict__ fy,
+                          const double* __restrict__ fz, double* __restrict__ cx, double* __restrict__ cy,
+                          double* __restrict__ cz, int fnx, int fny, int cnx, int cny, int cnz) {
+    const size_t total = (size_t)cnx * cny * cnz;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const int I = (int)(t % cnx);
+        const size_t r = t / cnx;
+        const int J = (int)(r % cny), K = (int)(r / cny);
+        const size_t f000 = cidx(2 * I, 2 * J, 2 * K, fnx, fny);
+        const size_t dy = fnx, dz = (size_t)fnx * fny;
+        cx[t] = 0.25 * ((fx[f000] + fx[f000 + dy]) + (fx[f000 + dz] + fx[f000 + dz + dy]));
+        cy[t] = 0.25 * ((fy[f000] + fy[f000 + 1]) + (fy[f000 + dz] + fy[f000 + dz + 1]));
+        cz[t] = 0.25 * ((fz[f000] + fz[f000 + 1]) + (fz[f000 + dy] + fz[f000 + dy + 1]));
     }
 }
 
 // Cell weight = mean of beta over the cell's interior faces (x-, x+, y-, y+, z-, z+).
-__global__ void k_cell_weights(const double* __restrict__ bx, const double* __restrict__ by,
-                               const double* __restrict__ bz, double* __restrict__ a, int nx, int ny, int nz) {
-    size_t total = (size_t)nx * ny * nz;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (size_t)gridDim.x * blockDim.x) {
-        int i = (int)(t % nx);
-        size_t r = t / nx;
-        int j = (int)(r % ny), k = (int)(r / ny);
+__global__ void k_cell_weights(Lvl<double> L, double* __restrict__ a) {
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const size_t total = (size_t)nx * ny * nz;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % nx);
+        const size_t r = t / nx;
+        const int j = (int)(r % ny), k = (int)(r / ny);
+        double w0, w1, w2, w3, w4, w5;
+        faces6(L, i, j, k, t, w0, w1, w2, w3, w4, w5);
         double s = 0;
         int cnt = 0;
-        if (i > 0) { s += bx[fxi(i, j, k, nx, ny)]; cnt++; }
-        if (i < nx - 1) { s += bx[fxi(i + 1, j, k, nx, ny)]; cnt++; }
-        if (j > 0) { s += by[fyi(i, j, k, nx, ny)]; cnt++; }
-        if (j < ny - 1) { s += by[fyi(i, j + 1, k, nx, ny)]; cnt++; }
-        if (k > 0) { s += bz[fzi(i, j, k, nx, ny)]; cnt++; }
-        if (k < nz - 1) { s += bz[fzi(i, j, k + 1, nx, ny)]; cnt++; }
+        if (i > 0) { s += w0; cnt++; }
+        if (i < nx - 1) { s += w1; cnt++; }
+        if (j > 0) { s += w2; cnt++; }
+        if (j < ny - 1) { s += w3; cnt++; }
+        if (k > 0) { s += w4; cnt++; }
+        if (k < nz - 1) { s += w5; cnt++; }
         a[t] = cnt ? s / cnt : 1.0;
     }
 }
@@ -288,11 +303,9 @@ __global__ void k_cell_weights(const double* __restrict__ bx, const double* __re
 // B in global memory, n <= 512): assemble, then in-place Gauss-Jordan without
 // pivoting (B is symmetric positive definite, every pivot is positive).
 // *bad is incremented if a pivot is not positive.
-__global__ void __launch_bounds__(FIN_THREADS) k_coarse_invert(const double* __restrict__ bx,
-                                                               const double* __restrict__ by,
-                                                               const double* __restrict__ bz, int nx, int ny,
-                                                               int nz, double* __restrict__ B,
+__global__ void __launch_bounds__(FIN_THREADS) k_coarse_invert(Lvl<double> L, double* __restrict__ B,
                                                                int* __restrict__ bad) {
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
     __shared__ double rowk[512];
     __shared__ double colk[512];
     __shared__ double red[FIN_THREADS / 64];
@@ -303,13 +316,15 @@ __global__ void __launch_bounds__(FIN_THREADS) k_coarse_invert(const double* __r
     double dsum = 0;
     for (int c = tid; c < n; c += FIN_THREADS) {
         int i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+        double w0, w1, w2, w3, w4, w5;
+        faces6(L, i, j, k, (size_t)c, w0, w1, w2, w3, w4, w5);
         double dg = 0;
-        if (i > 0) { double w = bx[fxi(i, j, k, nx, ny)]; dg += w; B[(size_t)c * n + c - 1] = -w; }
-        if (i < nx - 1) { double w = bx[fxi(i + 1, j, k, nx, ny)]; dg += w; B[(size_t)c * n + c + 1] = -w; }
-        if (j > 0) { double w = by[fyi(i, j, k, nx, ny)]; dg += w; B[(size_t)c * n + c - nx] = -w; }
-        if (j < ny - 1) { double w = by[fyi(i, j + 1, k, nx, ny)]; dg += w; B[(size_t)c * n + c + nx] = -w; }
-        if (k > 0) { double w = bz[fzi(i, j, k, nx, ny)]; dg += w; B[(size_t)c * n + c - nx * ny] = -w; }
-        if (k < nz - 1) { double w = bz[fzi(i, j, k + 1, nx, ny)]; dg += w; B[(size_t)c * n + c + nx * ny] = -w; }
+        if (i > 0) { dg += w0; B[(size_t)c * n + c - 1] = -w0; }
+        if (i < nx - 1) { dg += w1; B[(size_t)c * n + c + 1] = -w1; }
+        if (j > 0) { dg += w2; B[(size_t)c * n + c - nx] = -w2; }
+        if (j < ny - 1) { dg += w3; B[(size_t)c * n + c + nx] = -w3; }
+        if (k > 0) { dg += w4; B[(size_t)c * n + c - nx * ny] = -w4; }
+        if (k < nz - 1) { dg += w5; B[(size_t)c * n + c + nx * ny] = -w5; }
         B[(size_t)c * n + c] = dg;
         dsum += dg;
     }
@@ -367,87 +382,6 @@ __global__ void __launch_bounds__(BX* BY) k_rb_half(Lvl<T> L, T* __restrict__ p,
     }
 }
 
-// Residual r = b - L p restricted: rc(I,J,K) = 1/2 * sum of the 8 child residuals.
-template <class T>
-__global__ void __launch_bounds__(BX* BY) k_residual_restrict(Lvl<T> L, const T* __restrict__ p,
-                                                             const T* __restrict__ b, T* __restrict__ rc) {
-    const int cnx = L.nx / 2, cny = L.ny / 2, cnz = L.nz / 2;
-    const int I = blockIdx.x * BX + threadIdx.x, J = blockIdx.y * BY + threadIdx.y;
-    if (I >= cnx || J >= cny) return;
-    for (int K = blockIdx.z; K < cnz; K += gridDim.z) {
-        T acc = 0;
-        for (int c = 0; c < 2; c++)
-            for (int bb = 0; bb < 2; bb++)
-                for (int a = 0; a < 2; a++) {
-                    int i = 2 * I + a, j = 2 * J + bb, k = 2 * K + c;
-                    T s, d;
-                    nbsum(L, p, i, j, k, s, d);
-                    size_t cc = cidx(i, j, k, L.nx, L.ny);
-                    acc += b[cc] - (s - d * p[cc]);
-                }
-        rc[cidx(I, J, K, cnx, cny)] = T(0.5) * acc;
-    }
-}
-
-// Flux-conserving prolongation and correction: fine cell in octant s of coarse
-// cell C gets (1/8) * sum over T subset of {x,y,z} of the weight-averaged coarse
-// error over the 2^|T| coarse cells sharing the octant corner T (wall mirror
-// by index clamping).
-template <class T>
-__global__ void __launch_bounds__(BX* BY) k_prolong_add(const T* __restrict__ ec, const T* __restrict__ ac,
-                                                       int cnx, int cny, int cnz, T* __restrict__ ef) {
-    const int nx = 2 * cnx, ny = 2 * cny, nz = 2 * cnz;
-    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
-    if (i >= nx || j >= ny) return;
-    const int I = i >> 1, J = j >> 1;
-    const int Ix = (i & 1) ? min(I + 1, cnx - 1) : max(I - 1, 0);
-    const int Jy = (j & 1) ? min(J + 1, cny - 1) : max(J - 1, 0);
-    for (int k = blockIdx.z; k < nz; k += gridDim.z) {
-        const int K = k >> 1;
-        const int Kz = (k & 1) ? min(K + 1, cnz - 1) : max(K - 1, 0);
-        T av[8], wv[8];
-#pragma unroll
-        for (int dl = 0; dl < 8; dl++) {
-            int ci = (dl & 1) ? Ix : I, cj = (dl & 2) ? Jy : J, ck = (dl & 4) ? Kz : K;
-            size_t m = cidx(ci, cj, ck, cnx, cny);
-            av[dl] = ac[m];
-            wv[dl] = ac[m] * ec[m];
-        }
-        T total = 0;
-#pragma unroll
-        for (int Tm = 0; Tm < 8; Tm++) {
-            T num = 0, den = 0;
-#pragma unroll
-            for (int dl = 0; dl < 8; dl++) {
-                if (dl & ~Tm) continue;
-                num += wv[dl];
-                den += av[dl];
-            }
-            total += num / den;
-        }
-        size_t c = cidx(i, j, k, nx, ny);
-        ef[c] += total / T(8);
-    }
-}
-
-// Convergence check: partial sums of r^2 (r = b - L p) and of p, FP64 accumulation.
-template <class T>
-__global__ void __launch_bounds__(BX* BY) k_resid_norm(Lvl<T> L, const T* __restrict__ p,
-                                                      const T* __restrict__ b, double* __restrict__ part) {
-    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
-    double a = 0, q = 0;
-    if (i < L.nx && j < L.ny)
-        for (int k = blockIdx.z; k < L.nz; k += gridDim.z) {
-            T s, d;
-            nbsum(L, p, i, j, k, s, d);
-            size_t c = cidx(i, j, k, L.nx, L.ny);
-            double r = (double)(b[c] - (s - d * p[c]));
-            a += r * r;
-            q += (double)p[c];
-        }
-    block_partials2(a, q, part);
-}
-
 // Exact coarsest solve e = -B^{-1} (r - mean r), FP64 arithmetic; one block.
 template <class T>
 __global__ void __launch_bounds__(512) k_coarse_solve(const double* __restrict__ Binv, int n,
@@ -489,6 +423,17 @@ __device__ __forceinline__ int xcd_tile(int w, int nwg) {
     return x * q + min(x, r) + m;
 }
 
+template <class T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    using type = float2;
+};
+template <>
+struct Vec2<double> {
+    using type = double2;
+};
+
 // One full red-black Gauss-Seidel sweep (colour c0 first, then 1 - c0) in a
 // single pass over HBM, out of place (pin -> pout, so tiles never race).
 //
@@ -498,107 +443,145 @@ __device__ __forceinline__ int xcd_tile(int w, int nwg) {
 // same ones the neighbouring tile computes, bit for bit), so the second colour
 // can be updated on the tile from LDS alone.  At step t the first colour is
 // updated on plane t and the second colour on plane t-1, which is then final
-// and written out.  Thread (li, lj) owns ring-1 column (li, lj) and keeps that
-// column's face coefficients and right-hand side for two planes in registers.
-// Below plane k0 and above k1-1 the first colour is recomputed redundantly
-// (planes k0-1 and k1) so chunks are independent.  The global loads of plane
-// t+2 (pin) and t+1 (faces, b) are issued before the compute of step t and
-// written to LDS at the start of step t+1.
+// and written out.  Below plane k0 and above k1-1 the first colour is
+// recomputed redundantly (planes k0-1 and k1) so chunks are independent.
+//
+// Thread (q, lj) owns the aligned cell pair i = i0-2+2q, i0-1+2q of row
+// j = j0-1+lj (pairs q = 0 and TX/2+1 straddle the ring), so every global
+// access is a 2-element vector and each thread updates one cell of each colour
+// per plane: the first colour on plane t and the second colour on plane t-1
+// fall on the same cell of the pair.  Face coefficients and right-hand side of
+// the pair are kept in registers for two planes.  The global loads of plane
+// t+2 (pin) and t+1 (faces, b) are issued before the compute of step t.
+// Requires even nx (every smoothed level has one).
+//
+// With shift_sum non-null, every value of pin is first reduced by
+// shift_sum[0] / n_cells (the mean-zero projection of the previous iterate, done
+// on the fly instead of as a separate pass; same arithmetic as k_sub_mean).
 template <class T, int TX, int TY>
-__global__ void __launch_bounds__((TX + 2) * (TY + 2)) k_rb_sweep(Lvl<T> L, const T* __restrict__ pin,
-                                                                  T* __restrict__ pout, const T* __restrict__ b,
-                                                                  int c0, int kc, int tiles_x, int tiles_y) {
-    constexpr int W = TX + 4, H = TY + 4, NT = (TX + 2) * (TY + 2), NS = 5;
-    constexpr int NP = (H * W + NT - 1) / NT;  // ring cells loaded per thread
-    __shared__ T sp[NS][H][W];
+__global__ void __launch_bounds__((TX / 2 + 2) * (TY + 2)) k_rb_sweep(Lvl<T> L, const T* __restrict__ pin,
+                                                                      T* __restrict__ pout, const T* __restrict__ b,
+                                                                      int c0, int kc, int tiles_x, int tiles_y,
+                                                                      const double* __restrict__ shift_sum,
+                                                                      double n_cells) {
+    using V = typename Vec2<T>::type;
+    constexpr int W = TX + 4, H = TY + 4, PW = TX / 2 + 2, NT = PW * (TY + 2), NS = 5;
+    constexpr int NV = H * (W / 2);            // pairs in a staged plane
+    constexpr int NP = (NV + NT - 1) / NT;     // staged pairs per thread
+    __shared__ __align__(16) T sp[NS][H][W];
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, chunk = tile / (tiles_x * tiles_y);
     const int i0 = tx * TX, j0 = ty * TY;
     const int k0 = chunk * kc, k1 = min(nz, k0 + kc);
     const int tid = threadIdx.x;
-    const int li = tid % (TX + 2), lj = tid / (TX + 2);
-    const int gi = i0 + li - 1, gj = j0 + lj - 1;
-    const bool incell = gi >= 0 && gi < nx && gj >= 0 && gj < ny;
-    const bool interior = incell && li >= 1 && li <= TX && lj >= 1 && lj <= TY;
+    const int q = tid % PW, lj = tid / PW;
+    const int ia = i0 - 2 + 2 * q, gj = j0 - 1 + lj;     // first cell of the pair, row
+    const bool inpair = ia >= 0 && ia < nx && gj >= 0 && gj < ny;   // nx even: both cells in or both out
+    const bool interior = inpair && q >= 1 && q <= TX / 2 && lj >= 1 && lj <= TY;
     const size_t plane = (size_t)nx * ny;
+    const T shift = shift_sum ? (T)(shift_sum[0] / n_cells) : T(0);
 
-    // the ring cells this thread stages: offsets into a plane (-1 = outside the grid)
     long roff[NP];
     int rpos[NP];
 #pragma unroll
     for (int u = 0; u < NP; u++) {
-        const int q = tid + u * NT;
-        rpos[u] = q < H * W ? q : -1;
-        const int qi = q % W, qj = q / W;
-        const int ii = i0 + qi - 2, jj = j0 + qj - 2;
-        roff[u] = (q < H * W && ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? (long)jj * nx + ii : -1;
+        const int v = tid + u * NT;
+        const int vi = v % (W / 2), vj = v / (W / 2);
+        const int ii = i0 - 2 + 2 * vi, jj = j0 - 2 + vj;
+        rpos[u] = v < NV ? vj * W + 2 * vi : -1;
+        roff[u] = (v < NV && ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? (long)jj * nx + ii : -1;
     }
     T* const spf = &sp[0][0][0];
     auto slot = [](int k) { return (k + 2 * NS) % NS; };
-    auto fetch_ring = [&](int k, T* v) {
+    auto fetch_ring = [&](int k, V* v) {
         const bool kin = k >= 0 && k < nz;
 #pragma unroll
-        for (int u = 0; u < NP; u++) v[u] = (kin && roff[u] >= 0) ? pin[(size_t)k * plane + roff[u]] : T(0);
+        for (int u = 0; u < NP; u++) {
+            V x;
+            x.x = T(0);
+            x.y = T(0);
+            if (kin && roff[u] >= 0) {
+                x = *reinterpret_cast<const V*>(pin + (size_t)k * plane + roff[u]);
+                x.x -= shift;
+                x.y -= shift;
+            }
+            v[u] = x;
+        }
     };
-    auto store_ring = [&](int k, const T* v) {
+    auto store_ring = [&](int k, const V* v) {
         T* dst = spf + slot(k) * (H * W);
 #pragma unroll
         for (int u = 0; u < NP; u++)
-            if (rpos[u] >= 0) dst[rpos[u]] = v[u];
+            if (rpos[u] >= 0) *reinterpret_cast<V*>(dst + rpos[u]) = v[u];
     };
+    // face coefficients and right-hand side of the pair on one plane
     struct FB {
-        T w0, w1, w2, w3, w4, w5, bb;
+        V fx, fy, fyu, fz, fzu, bb;
+        T fxu;  // upper x-face of the second cell
     };
     auto fetch_fb = [&](int k) {
-        FB f{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
-        if (incell && k >= 0 && k < nz) {
-            f.w0 = L.bx[fxi(gi, gj, k, nx, ny)];
-            f.w1 = L.bx[fxi(gi + 1, gj, k, nx, ny)];
-            f.w2 = L.by[fyi(gi, gj, k, nx, ny)];
-            f.w3 = L.by[fyi(gi, gj + 1, k, nx, ny)];
-            f.w4 = L.bz[fzi(gi, gj, k, nx, ny)];
-            f.w5 = L.bz[fzi(gi, gj, k + 1, nx, ny)];
-            f.bb = b[(size_t)k * plane + (size_t)gj * nx + gi];
+        FB f;
+        const V z2{T(0), T(0)};
+        f.fx = f.fy = f.fyu = f.fz = f.fzu = f.bb = z2;
+        f.fxu = T(0);
+        if (inpair && k >= 0 && k < nz) {
+            const size_t c = (size_t)k * plane + (size_t)gj * nx + ia;
+            f.fx = *reinterpret_cast<const V*>(L.fx + c);
+            if (ia + 2 < nx) f.fxu = L.fx[c + 2];
+            f.fy = *reinterpret_cast<const V*>(L.fy + c);
+            if (gj + 1 < ny) f.fyu = *reinterpret_cast<const V*>(L.fy + c + nx);
+            f.fz = *reinterpret_cast<const V*>(L.fz + c);
+            if (k + 1 < nz) f.fzu = *reinterpret_cast<const V*>(L.fz + c + plane);
+            f.bb = *reinterpret_cast<const V*>(b + c);
         }
         return f;
     };
+    // Gauss-Seidel value of cell e (0: first of the pair) on a plane whose
+    // faces are f, neighbours from LDS slots of planes k-1, k, k+1.
+    auto gs = [&](const FB& f, int e, int k) {
+        const int col = 2 * q + e, row = lj + 1;
+        const T w0 = e ? f.fx.y : f.fx.x;
+        const T w1 = e ? f.fxu : f.fx.y;
+        const T w2 = e ? f.fy.y : f.fy.x;
+        const T w3 = e ? f.fyu.y : f.fyu.x;
+        const T w4 = e ? f.fz.y : f.fz.x;
+        const T w5 = e ? f.fzu.y : f.fzu.x;
+        const T bb = e ? f.bb.y : f.bb.x;
+        T(*c)[W] = sp[slot(k)];
+        const T s = stencil_sum(w0, w1, w2, w3, w4, w5, c[row][col - 1], c[row][col + 1], c[row - 1][col],
+                                c[row + 1][col], sp[slot(k - 1)][row][col], sp[slot(k + 1)][row][col]);
+        return (s - bb) / stencil_diag(w0, w1, w2, w3, w4, w5);
+    };
 
-    T ring[NP];
+    V ring[NP];
     fetch_ring(k0 - 2, ring);
     store_ring(k0 - 2, ring);
     fetch_ring(k0 - 1, ring);
     store_ring(k0 - 1, ring);
-    fetch_ring(k0, ring);              // plane t+1 for the first step
-    FB fnext = fetch_fb(k0 - 1);       // plane t for the first step
+    fetch_ring(k0, ring);
+    FB fnext = fetch_fb(k0 - 1);
     FB fcur, fprev = fnext;
     for (int t = k0 - 1; t <= k1; t++) {
         store_ring(t + 1, ring);
         fcur = fnext;
         lds_barrier();
-        fetch_ring(t + 2, ring);       // in flight during this step
+        fetch_ring(t + 2, ring);
         fnext = fetch_fb(t + 1);
-        if (incell && t >= 0 && t < nz && (((gi + gj + t) & 1) == c0)) {
-            T(*c)[W] = sp[slot(t)];
-            const T s = stencil_sum(fcur.w0, fcur.w1, fcur.w2, fcur.w3, fcur.w4, fcur.w5, c[lj + 1][li],
-                                    c[lj + 1][li + 2], c[lj][li + 1], c[lj + 2][li + 1],
-                                    sp[slot(t - 1)][lj + 1][li + 1], sp[slot(t + 1)][lj + 1][li + 1]);
-            c[lj + 1][li + 1] = (s - fcur.bb) / stencil_diag(fcur.w0, fcur.w1, fcur.w2, fcur.w3, fcur.w4, fcur.w5);
-        }
+        // the cell of the pair that has the first colour on plane t (and the
+        // second colour on plane t-1)
+        const int e = (c0 + i0 + gj + t) & 1;
+        const int col = 2 * q + e;
+        if (inpair && t >= 0 && t < nz && col >= 1 && col <= TX + 2) sp[slot(t)][lj + 1][col] = gs(fcur, e, t);
         lds_barrier();
         const int tp = t - 1;
         if (interior && tp >= k0 && tp < k1) {
-            T(*c)[W] = sp[slot(tp)];
-            T v;
-            if (((gi + gj + tp) & 1) != c0) {
-                const T s = stencil_sum(fprev.w0, fprev.w1, fprev.w2, fprev.w3, fprev.w4, fprev.w5, c[lj + 1][li],
-                                        c[lj + 1][li + 2], c[lj][li + 1], c[lj + 2][li + 1],
-                                        sp[slot(tp - 1)][lj + 1][li + 1], sp[slot(tp + 1)][lj + 1][li + 1]);
-                v = (s - fprev.bb) / stencil_diag(fprev.w0, fprev.w1, fprev.w2, fprev.w3, fprev.w4, fprev.w5);
-            } else {
-                v = c[lj + 1][li + 1];
-            }
-            pout[(size_t)tp * plane + (size_t)gj * nx + gi] = v;
+            const T vnew = gs(fprev, e, tp);
+            const T vold = sp[slot(tp)][lj + 1][2 * q + (e ^ 1)];
+            V out;
+            out.x = e ? vold : vnew;
+            out.y = e ? vnew : vold;
+            *reinterpret_cast<V*>(pout + (size_t)tp * plane + (size_t)gj * nx + ia) = out;
         }
         fprev = fcur;
     }
@@ -637,11 +620,8 @@ __device__ __forceinline__ Plane1<T> load_plane1(const Lvl<T>& L, const T* __res
     v.ps = j > 0 ? p[c - nx] : T(0);
     v.pn = j < ny - 1 ? p[c + nx] : T(0);
     v.b = b[c];
-    v.wx0 = L.bx[fxi(i, j, k, nx, ny)];
-    v.wx1 = L.bx[fxi(i + 1, j, k, nx, ny)];
-    v.wy0 = L.by[fyi(i, j, k, nx, ny)];
-    v.wy1 = L.by[fyi(i, j + 1, k, nx, ny)];
-    v.wz1 = L.bz[fzi(i, j, k + 1, nx, ny)];
+    T wz0;
+    faces6(L, i, j, k, c, v.wx0, v.wx1, v.wy0, v.wy1, wz0, v.wz1);
     return v;
 }
 
@@ -661,7 +641,7 @@ __global__ void __launch_bounds__(CBX* CBY) k_resid_col(Lvl<T> L, const T* __res
         const size_t plane = (size_t)nx * ny;
         const size_t col = (size_t)j * nx + i;
         T pbelow = k0 > 0 ? p[(size_t)(k0 - 1) * plane + col] : T(0);
-        T wz0 = L.bz[fzi(i, j, k0, nx, ny)];
+        T wz0 = L.fz[(size_t)k0 * plane + col];
         Plane1<T> cur = load_plane1(L, p, b, i, j, k0);
         Plane1<T> nxt = cur;
         for (int k = k0; k < k1; k++) {
@@ -721,7 +701,7 @@ __global__ void __launch_bounds__(256) k_resid_restrict_col(Lvl<T> L, const T* _
     Plane1<T> cur{}, nxt{};
     if (active && k0 < k1) {
         pbelow = k0 > 0 ? p[(size_t)(k0 - 1) * plane + col] : T(0);
-        wz0 = L.bz[fzi(i, j, k0, nx, ny)];
+        wz0 = L.fz[(size_t)k0 * plane + col];
         cur = load_plane1(L, p, b, i, j, k0);
     }
     T acc = 0;
@@ -747,41 +727,76 @@ __global__ void __launch_bounds__(256) k_resid_restrict_col(Lvl<T> L, const T* _
     }
 }
 
-// FP64 refinement residual: r = b - L p (FP64), r32 = float(r * inv_s), partial sums
-// of r^2 and of p.
-__global__ void __launch_bounds__(BX* BY) k_refine_residual(Lvl<double> L, const double* __restrict__ p,
-                                                           const double* __restrict__ b, double inv_s,
-                                                           float* __restrict__ r32, double* __restrict__ part) {
-    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
-    double a = 0, q = 0;
-    if (i < L.nx && j < L.ny)
-        for (int k = blockIdx.z; k < L.nz; k += gridDim.z) {
-            double s, d;
-            nbsum(L, p, i, j, k, s, d);
-            size_t c = cidx(i, j, k, L.nx, L.ny);
-            double r = b[c] - (s - d * p[c]);
-            r32[c] = (float)(r * inv_s);
-            a += r * r;
-            q += p[c];
+// Flux-conserving prolongation and correction, z-marching: thread (i, j) owns
+// one fine column.  Its octant side in x and y is fixed, so the coarse cells it
+// needs are the 2 x 2 columns (I or Ix) x (J or Jy); along z it keeps three
+// coarse planes (a and a*e) in registers and advances one coarse plane every
+// two fine planes.  V_T = sum a e / sum a over the corner's cells; the corner
+// T = {} is the coarse cell itself, V = e_C.
+template <class T>
+__global__ void __launch_bounds__(CBX* CBY) k_prolong_col(const T* __restrict__ ec, const T* __restrict__ ac,
+                                                         int cnx, int cny, int cnz, ColGrid G, T* __restrict__ ef) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
+    const int nx = 2 * cnx, ny = 2 * cny, nz = 2 * cnz;
+    const int i = tx * CBX + (int)(threadIdx.x % CBX), j = ty * CBY + (int)(threadIdx.x / CBX);
+    const int k0 = chunk * G.kc, k1 = min(nz, k0 + G.kc);
+    if (i >= nx || j >= ny || k0 >= k1) return;
+    const int I = i >> 1, J = j >> 1;
+    const int Ix = (i & 1) ? min(I + 1, cnx - 1) : max(I - 1, 0);
+    const int Jy = (j & 1) ? min(J + 1, cny - 1) : max(J - 1, 0);
+    const size_t cplane = (size_t)cnx * cny;
+    const size_t o00 = (size_t)J * cnx + I, o10 = (size_t)J * cnx + Ix, o01 = (size_t)Jy * cnx + I,
+                 o11 = (size_t)Jy * cnx + Ix;
+    // coarse plane K: a[4], w[4] = a*e for cells (I,J), (Ix,J), (I,Jy), (Ix,Jy)
+    struct CP {
+        T a0, a1, a2, a3, w0, w1, w2, w3, e0;
+    };
+    auto load = [&](int K) {
+        CP c;
+        const size_t base = (size_t)K * cplane;
+        c.a0 = ac[base + o00]; c.a1 = ac[base + o10]; c.a2 = ac[base + o01]; c.a3 = ac[base + o11];
+        c.e0 = ec[base + o00];
+        c.w0 = c.a0 * c.e0;
+        c.w1 = c.a1 * ec[base + o10];
+        c.w2 = c.a2 * ec[base + o01];
+        c.w3 = c.a3 * ec[base + o11];
+        return c;
+    };
+    int Kc = k0 >> 1;
+    CP cm = load(max(Kc - 1, 0)), c0 = load(Kc), cp = load(min(Kc + 1, cnz - 1));
+    const size_t fplane = (size_t)nx * ny;
+    for (int k = k0; k < k1; k++) {
+        const int K = k >> 1;
+        if (K != Kc) {
+            Kc = K;
+            cm = c0;
+            c0 = cp;
+            cp = load(min(K + 1, cnz - 1));
         }
-    block_partials2(a, q, part);
+        const CP& cz = (k & 1) ? cp : cm;   // the coarse plane on this child's z side
+        // corners: {}, {x}, {y}, {x,y}, then the same with z
+        T tot = c0.e0;
+        tot += (c0.w0 + c0.w1) / (c0.a0 + c0.a1);
+        tot += (c0.w0 + c0.w2) / (c0.a0 + c0.a2);
+        tot += (((c0.w0 + c0.w1) + c0.w2) + c0.w3) / (((c0.a0 + c0.a1) + c0.a2) + c0.a3);
+        tot += (c0.w0 + cz.w0) / (c0.a0 + cz.a0);
+        tot += (((c0.w0 + c0.w1) + cz.w0) + cz.w1) / (((c0.a0 + c0.a1) + cz.a0) + cz.a1);
+        tot += (((c0.w0 + c0.w2) + cz.w0) + cz.w2) / (((c0.a0 + c0.a2) + cz.a0) + cz.a2);
+        tot += (((((((c0.w0 + c0.w1) + c0.w2) + c0.w3) + cz.w0) + cz.w1) + cz.w2) + cz.w3) /
+               (((((((c0.a0 + c0.a1) + c0.a2) + c0.a3) + cz.a0) + cz.a1) + cz.a2) + cz.a3);
+        const size_t f = (size_t)k * fplane + (size_t)j * nx + i;
+        ef[f] += tot / T(8);
+    }
 }
 
-// FP64 update p += s * e32; partial sums of the updated p (for the mean) and of e^2.
-__global__ void __launch_bounds__(BX* BY) k_refine_update(double* __restrict__ p, const float* __restrict__ e,
-                                                         double s, int nx, int ny, int nz,
-                                                         double* __restrict__ part) {
-    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
-    double a = 0, q = 0;
-    if (i < nx && j < ny)
-        for (int k = blockIdx.z; k < nz; k += gridDim.z) {
-            size_t c = cidx(i, j, k, nx, ny);
-            double v = p[c] + s * (double)e[c];
-            p[c] = v;
-            a += v;
-            q += (double)e[c] * (double)e[c];
-        }
-    block_partials2(a, q, part);
+// FP64 update p = (p - mean) + s * e32, the mean being shift_sum[0] / N (the
+// mean-zero projection of the previous iterate, folded into this pass).
+__global__ void k_refine_update(double* __restrict__ p, const float* __restrict__ e, double s, size_t n,
+                                const double* __restrict__ shift_sum) {
+    const double c = shift_sum[0] / (double)n;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        p[t] = (p[t] - c) + s * (double)e[t];
 }
 
 }  // namespace mgk
