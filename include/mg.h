@@ -86,10 +86,10 @@ typedef struct {
                         ping-pong buffer.  Every choice gives bit-identical results. */
 } mg_options;
 
-/* Fused sweep variants: tile (cells) 64x8, 128x4, 128x8, 64x16, each with a
-   target of about 1024 (odd) or 4096 (even) workgroups: variant v uses tile
-   (v-1)/2 and target (v-1)%2. */
-#define MG_NUM_TILES 8
+/* Fused sweep variants: variant v uses tile (v-1)/2 of the list 64x8, 128x4,
+   128x8, 64x16 (one sweep per pass), 64x4, 64x8 (two sweeps per pass), with a
+   target of about 1024 (v odd) or 4096 (v even) workgroups. */
+#define MG_NUM_TILES 12
 
 /* Kernel classes reported in mg_stats when options.profile is set. */
 enum {

@@ -38,6 +38,12 @@ void set_error(const std::string& msg) { g_err = msg; }
         }                                                                                     \
     } while (0)
 
+#define HIPCHK_VOID(expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) set_error(std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 dim3 col_grid(int nx, int ny, int nz) {
@@ -337,7 +343,7 @@ struct Hier {
     const T* a[MG_MAX_LEVELS];
 };
 
-template <class T, int TX, int TY>
+template <class T, int TX, int TY, int NSW>
 static void launch_sweep(hipStream_t s, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0, int target,
                          const double* shift_sum) {
     const int gx = (L.nx + TX - 1) / TX, gy = (L.ny + TY - 1) / TY;
@@ -346,20 +352,26 @@ static void launch_sweep(hipStream_t s, const Lvl<T>& L, const T* pin, T* pout, 
     int chunks = std::max(1, std::min(std::max(1, L.nz / 8), (target + tiles - 1) / tiles));
     const int kc = (L.nz + chunks - 1) / chunks;
     chunks = (L.nz + kc - 1) / kc;
-    k_rb_sweep<T, TX, TY><<<dim3(tiles * chunks), (TX / 2 + 2) * (TY + 2), 0, s>>>(
-        L, pin, pout, b, c0, kc, gx, gy, shift_sum, (double)L.nx * L.ny * L.nz);
+    constexpr int NT = (TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2);
+    k_rb_sweep<T, TX, TY, NSW><<<dim3(tiles * chunks), NT, 0, s>>>(L, pin, pout, b, c0, kc, gx, gy, shift_sum,
+                                                                  (double)L.nx * L.ny * L.nz);
 }
 
-// Fused sweep variant v in 1..MG_NUM_TILES.
+// Sweeps done by one pass of fused variant v (1..MG_NUM_TILES).
+static int sweeps_per_pass(int v) { return v > 8 ? 2 : 1; }
+
+// Fused sweep variant v in 1..MG_NUM_TILES: one pass doing sweeps_per_pass(v) sweeps.
 template <class T>
 static void fused_sweep(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0,
                         const double* shift_sum = nullptr) {
     const int target = ((v - 1) & 1) ? 4096 : 1024;
     switch ((v - 1) >> 1) {
-        case 0: launch_sweep<T, 64, 8>(s, L, pin, pout, b, c0, target, shift_sum); break;
-        case 1: launch_sweep<T, 128, 4>(s, L, pin, pout, b, c0, target, shift_sum); break;
-        case 2: launch_sweep<T, 128, 8>(s, L, pin, pout, b, c0, target, shift_sum); break;
-        default: launch_sweep<T, 64, 16>(s, L, pin, pout, b, c0, target, shift_sum); break;
+        case 0: launch_sweep<T, 64, 8, 1>(s, L, pin, pout, b, c0, target, shift_sum); break;
+        case 1: launch_sweep<T, 128, 4, 1>(s, L, pin, pout, b, c0, target, shift_sum); break;
+        case 2: launch_sweep<T, 128, 8, 1>(s, L, pin, pout, b, c0, target, shift_sum); break;
+        case 3: launch_sweep<T, 64, 16, 1>(s, L, pin, pout, b, c0, target, shift_sum); break;
+        case 4: launch_sweep<T, 64, 4, 2>(s, L, pin, pout, b, c0, target, shift_sum); break;
+        default: launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum); break;
     }
 }
 
@@ -452,6 +464,7 @@ static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b
             (void)hipEventElapsedTime(&ms, e0, e1);
             tmin = std::min(tmin, ms);
         }
+        if (v > 0) tmin /= sweeps_per_pass(v);
         if (tmin < best) {
             best = tmin;
             bestv = v;
@@ -466,42 +479,42 @@ static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b
     return MG_OK;
 }
 
-// nsweep red-black sweeps on level l, first colour c0 (0: red first): pairs of
-// fused out-of-place sweeps (ping-pong through tmp), then one in-place sweep of
-// the reference kernels if nsweep is odd or the level uses them throughout.
-// shift_sum (optional): the first fused sweep subtracts shift_sum[0]/N from the
-// iterate as it reads it; returns false if there was no fused sweep to do so.
+// nsweep red-black sweeps on level l, first colour c0 (0: red first): passes of
+// the level's fused variant (each pass does sweeps_per_pass sweeps, out of
+// place: cur -> alt, then the two pointers swap), then in-place sweeps of the
+// reference kernels for what is left (or for everything, on levels that use
+// them).  shift_sum (optional): the first fused pass subtracts shift_sum[0]/N
+// from the iterate as it reads it; returns false if there was no fused pass.
 template <class T>
-static bool smooth(mg_handle* h, Hier<T>& H, int l, int nsweep, int c0, const double* shift_sum = nullptr) {
+static bool smooth(mg_handle* h, Hier<T>& H, int l, int nsweep, int c0, T*& cur, T*& alt,
+                   const double* shift_sum = nullptr) {
     if (nsweep <= 0) return shift_sum == nullptr;
     hipStream_t s = h->stream;
     const LevelDims& d = H.d[l];
     const int cls = l == 0 ? MG_K_SMOOTH_FINE : MG_K_SMOOTH;
     const double full = (3.0 * d.ncell() + d.nfaces()) * sizeof(T);
-    const int tile = H.tmp[l] ? h->tile[l] : -1;
+    const int tile = alt ? h->tile[l] : -1;
     bool shifted = shift_sum == nullptr;
     int rem = nsweep;
     if (tile > 0) {
-        for (; rem >= 2; rem -= 2) {
-            {
-                Prof pf(h, cls, full);
-                fused_sweep<T>(s, tile, H.L[l], H.e[l], H.tmp[l], H.rhs[l], c0, shifted ? nullptr : shift_sum);
-                shifted = true;
-            }
+        const int spp = sweeps_per_pass(tile);
+        for (; rem >= spp; rem -= spp) {
             Prof pf(h, cls, full);
-            fused_sweep<T>(s, tile, H.L[l], H.tmp[l], H.e[l], H.rhs[l], c0);
+            fused_sweep<T>(s, tile, H.L[l], cur, alt, H.rhs[l], c0, shifted ? nullptr : shift_sum);
+            shifted = true;
+            std::swap(cur, alt);
         }
     }
     for (; rem > 0; rem--) {
         Prof pf(h, cls, full);
-        ref_sweep<T>(s, H.L[l], H.e[l], H.rhs[l], c0);
+        ref_sweep<T>(s, H.L[l], cur, H.rhs[l], c0);
     }
     return shifted;
 }
 
 // True when the first pre-smoothing pass on level 0 can absorb the mean shift.
 static bool fused_first_sweep(const mg_handle* h) {
-    return h->L.nlev > 1 && h->tile[0] > 0 && h->o.nu1 >= 2;
+    return h->L.nlev > 1 && h->tile[0] > 0 && h->o.nu1 >= sweeps_per_pass(h->tile[0]);
 }
 
 template <class T>
@@ -513,13 +526,16 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
         k_coarse_solve<T><<<1, 512, 0, s>>>(h->binv, h->L.ncoarse, H.rhs[l], H.e[l]);
         return;
     }
-    smooth(h, H, l, h->o.nu1, 0, shift_sum);
+    // the current iterate moves between e and tmp as fused passes run
+    T* cur = H.e[l];
+    T* alt = H.tmp[l];
+    smooth(h, H, l, h->o.nu1, 0, cur, alt, shift_sum);
     const LevelDims& c = H.d[l + 1];
     {
         Prof pf(h, MG_K_RESTRICT, ((2.0 * d.ncell() + d.nfaces()) + c.ncell()) * sizeof(T));
         int nb = 0;
         const ColGrid G = rgrid(d.nx, d.ny, d.nz, &nb);
-        k_resid_restrict_col<T><<<nb, 256, 0, s>>>(H.L[l], H.e[l], H.rhs[l], G, H.rhs[l + 1]);
+        k_resid_restrict_col<T><<<nb, 256, 0, s>>>(H.L[l], cur, H.rhs[l], G, H.rhs[l + 1]);
     }
     {
         Prof pf(h, MG_K_OTHER, (double)c.ncell() * sizeof(T));
@@ -530,9 +546,13 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
         Prof pf(h, MG_K_PROLONG, (2.0 * d.ncell() + 2.0 * c.ncell()) * sizeof(T));
         int nbp = 0;
         const ColGrid G = zgrid(d.nx, d.ny, d.nz, false, &nbp);
-        k_prolong_col<T><<<nbp, CBX * CBY, 0, s>>>(H.e[l + 1], H.a[l + 1], c.nx, c.ny, c.nz, G, H.e[l]);
+        k_prolong_col<T><<<nbp, CBX * CBY, 0, s>>>(H.e[l + 1], H.a[l + 1], c.nx, c.ny, c.nz, G, cur);
     }
-    smooth(h, H, l, h->o.nu2, 1);
+    smooth(h, H, l, h->o.nu2, 1, cur, alt);
+    if (cur != H.e[l]) {
+        Prof pf(h, MG_K_OTHER, 2.0 * d.ncell() * sizeof(T));
+        HIPCHK_VOID(hipMemcpyAsync(H.e[l], cur, d.ncell() * sizeof(T), hipMemcpyDeviceToDevice, s));
+    }
 }
 
 static double pow2_near(double v) {

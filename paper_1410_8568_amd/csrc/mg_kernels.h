@@ -434,40 +434,40 @@ struct Vec2<double> {
     using type = double2;
 };
 
-// One full red-black Gauss-Seidel sweep (colour c0 first, then 1 - c0) in a
-// single pass over HBM, out of place (pin -> pout, so tiles never race).
+// NSW full red-black Gauss-Seidel sweeps (each colour c0 first, then 1 - c0)
+// in a single pass over HBM, out of place (pin -> pout, so tiles never race).
 //
 // A workgroup owns a TX x TY column of cells and marches upward through a chunk
-// of kc planes.  Planes of pin are staged in LDS with a 2-cell ring; the first
-// colour is updated on the tile plus a 1-cell ring (the ring values are the
-// same ones the neighbouring tile computes, bit for bit), so the second colour
-// can be updated on the tile from LDS alone.  At step t the first colour is
-// updated on plane t and the second colour on plane t-1, which is then final
-// and written out.  Below plane k0 and above k1-1 the first colour is
-// recomputed redundantly (planes k0-1 and k1) so chunks are independent.
+// of kc planes.  The sweeps are 2*NSW colour stages; stage h (h = 1 .. R,
+// R = 2*NSW) updates colour c0 (h odd) or 1 - c0 (h even) on plane t - h + 1
+// at step t, on the tile plus a ring of R - h cells.  Planes of pin are staged
+// in LDS with an R-cell ring and updated in place stage by stage; a ring value
+// is the same one the neighbouring tile computes, bit for bit, so after stage R
+// the tile's plane t - R + 1 is final and written out.  Planes below k0 and
+// above k1 - 1 are recomputed redundantly, so chunks are independent.
 //
-// Thread (q, lj) owns the aligned cell pair i = i0-2+2q, i0-1+2q of row
-// j = j0-1+lj (pairs q = 0 and TX/2+1 straddle the ring), so every global
-// access is a 2-element vector and each thread updates one cell of each colour
-// per plane: the first colour on plane t and the second colour on plane t-1
-// fall on the same cell of the pair.  Face coefficients and right-hand side of
-// the pair are kept in registers for two planes.  The global loads of plane
+// Thread (q, lj) owns the aligned cell pair i = i0-R+2q, i0-R+1+2q of row
+// j = j0-R+1+lj, so every global access is a 2-element vector; at step t all
+// R stages fall on the same cell of the pair (the colour of a column flips
+// from plane to plane).  The face coefficients and right-hand side of the pair
+// are kept in registers for the R planes in flight.  The global loads of plane
 // t+2 (pin) and t+1 (faces, b) are issued before the compute of step t.
 // Requires even nx (every smoothed level has one).
 //
 // With shift_sum non-null, every value of pin is first reduced by
 // shift_sum[0] / n_cells (the mean-zero projection of the previous iterate, done
 // on the fly instead of as a separate pass; same arithmetic as k_sub_mean).
-template <class T, int TX, int TY>
-__global__ void __launch_bounds__((TX / 2 + 2) * (TY + 2)) k_rb_sweep(Lvl<T> L, const T* __restrict__ pin,
-                                                                      T* __restrict__ pout, const T* __restrict__ b,
-                                                                      int c0, int kc, int tiles_x, int tiles_y,
-                                                                      const double* __restrict__ shift_sum,
-                                                                      double n_cells) {
+template <class T, int TX, int TY, int NSW>
+__global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
+    k_rb_sweep(Lvl<T> L, const T* __restrict__ pin, T* __restrict__ pout, const T* __restrict__ b, int c0, int kc,
+               int tiles_x, int tiles_y, const double* __restrict__ shift_sum, double n_cells) {
     using V = typename Vec2<T>::type;
-    constexpr int W = TX + 4, H = TY + 4, PW = TX / 2 + 2, NT = PW * (TY + 2), NS = 5;
-    constexpr int NV = H * (W / 2);            // pairs in a staged plane
-    constexpr int NP = (NV + NT - 1) / NT;     // staged pairs per thread
+    constexpr int R = 2 * NSW;                  // LDS ring = number of colour stages
+    constexpr int W = TX + 2 * R, H = TY + 2 * R;
+    constexpr int PW = TX / 2 + R, PH = TY + 2 * (R - 1), NT = PW * PH;
+    constexpr int NS = R + 3;                   // plane slots: R + 2 live, one being refilled
+    constexpr int NV = H * (W / 2);             // pairs in a staged plane
+    constexpr int NP = (NV + NT - 1) / NT;      // staged pairs per thread
     __shared__ __align__(16) T sp[NS][H][W];
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -476,9 +476,9 @@ __global__ void __launch_bounds__((TX / 2 + 2) * (TY + 2)) k_rb_sweep(Lvl<T> L, 
     const int k0 = chunk * kc, k1 = min(nz, k0 + kc);
     const int tid = threadIdx.x;
     const int q = tid % PW, lj = tid / PW;
-    const int ia = i0 - 2 + 2 * q, gj = j0 - 1 + lj;     // first cell of the pair, row
+    const int ia = i0 - R + 2 * q, gj = j0 - R + 1 + lj;      // first cell of the pair, row
+    const int row = lj + 1;                                   // LDS row of this thread
     const bool inpair = ia >= 0 && ia < nx && gj >= 0 && gj < ny;   // nx even: both cells in or both out
-    const bool interior = inpair && q >= 1 && q <= TX / 2 && lj >= 1 && lj <= TY;
     const size_t plane = (size_t)nx * ny;
     const T shift = shift_sum ? (T)(shift_sum[0] / n_cells) : T(0);
 
@@ -488,12 +488,12 @@ __global__ void __launch_bounds__((TX / 2 + 2) * (TY + 2)) k_rb_sweep(Lvl<T> L, 
     for (int u = 0; u < NP; u++) {
         const int v = tid + u * NT;
         const int vi = v % (W / 2), vj = v / (W / 2);
-        const int ii = i0 - 2 + 2 * vi, jj = j0 - 2 + vj;
+        const int ii = i0 - R + 2 * vi, jj = j0 - R + vj;
         rpos[u] = v < NV ? vj * W + 2 * vi : -1;
         roff[u] = (v < NV && ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? (long)jj * nx + ii : -1;
     }
     T* const spf = &sp[0][0][0];
-    auto slot = [](int k) { return (k + 2 * NS) % NS; };
+    auto slot = [](int k) { return (k + 4 * NS) % NS; };
     auto fetch_ring = [&](int k, V* v) {
         const bool kin = k >= 0 && k < nz;
 #pragma unroll
@@ -537,10 +537,9 @@ __global__ void __launch_bounds__((TX / 2 + 2) * (TY + 2)) k_rb_sweep(Lvl<T> L, 
         }
         return f;
     };
-    // Gauss-Seidel value of cell e (0: first of the pair) on a plane whose
-    // faces are f, neighbours from LDS slots of planes k-1, k, k+1.
+    // Gauss-Seidel value of cell e (0: first of the pair) on plane k with faces f.
     auto gs = [&](const FB& f, int e, int k) {
-        const int col = 2 * q + e, row = lj + 1;
+        const int col = 2 * q + e;
         const T w0 = e ? f.fx.y : f.fx.x;
         const T w1 = e ? f.fxu : f.fx.y;
         const T w2 = e ? f.fy.y : f.fy.x;
@@ -555,35 +554,48 @@ __global__ void __launch_bounds__((TX / 2 + 2) * (TY + 2)) k_rb_sweep(Lvl<T> L, 
     };
 
     V ring[NP];
-    fetch_ring(k0 - 2, ring);
-    store_ring(k0 - 2, ring);
-    fetch_ring(k0 - 1, ring);
-    store_ring(k0 - 1, ring);
-    fetch_ring(k0, ring);
-    FB fnext = fetch_fb(k0 - 1);
-    FB fcur, fprev = fnext;
-    for (int t = k0 - 1; t <= k1; t++) {
+    const int tfirst = k0 - R + 1, tlast = k1 + R - 2;
+    fetch_ring(tfirst - 1, ring);
+    store_ring(tfirst - 1, ring);
+    fetch_ring(tfirst, ring);
+    store_ring(tfirst, ring);
+    fetch_ring(tfirst + 1, ring);
+    FB fq[R];                 // fq[h-1]: faces of plane t-h+1 during step t
+    FB fnext = fetch_fb(tfirst);
+#pragma unroll
+    for (int h = 0; h < R; h++) fq[h] = fnext;
+    for (int t = tfirst; t <= tlast; t++) {
         store_ring(t + 1, ring);
-        fcur = fnext;
+#pragma unroll
+        for (int h = R - 1; h > 0; h--) fq[h] = fq[h - 1];
+        fq[0] = fnext;
         lds_barrier();
         fetch_ring(t + 2, ring);
         fnext = fetch_fb(t + 1);
-        // the cell of the pair that has the first colour on plane t (and the
-        // second colour on plane t-1)
+        // the cell of the pair that stage 1 updates on plane t; every stage of
+        // this step updates the same cell (on its own plane)
         const int e = (c0 + i0 + gj + t) & 1;
         const int col = 2 * q + e;
-        if (inpair && t >= 0 && t < nz && col >= 1 && col <= TX + 2) sp[slot(t)][lj + 1][col] = gs(fcur, e, t);
-        lds_barrier();
-        const int tp = t - 1;
-        if (interior && tp >= k0 && tp < k1) {
-            const T vnew = gs(fprev, e, tp);
-            const T vold = sp[slot(tp)][lj + 1][2 * q + (e ^ 1)];
-            V out;
-            out.x = e ? vold : vnew;
-            out.y = e ? vnew : vold;
-            *reinterpret_cast<V*>(pout + (size_t)tp * plane + (size_t)gj * nx + ia) = out;
+#pragma unroll
+        for (int h = 1; h <= R; h++) {
+            const int z = t - h + 1;       // this stage's plane
+            const int rg = R - h;          // this stage's ring width
+            const bool in_ring = col >= R - rg && col < R + TX + rg && row >= R - rg && row < R + TY + rg;
+            const bool in_z = z >= 0 && z < nz && z >= k0 - rg && z < k1 + rg;
+            if (h < R) {
+                if (inpair && in_ring && in_z) sp[slot(z)][row][col] = gs(fq[h - 1], e, z);
+                lds_barrier();
+            } else if (inpair && in_ring && in_z) {
+                // the tile's plane z is final: this cell from stage R, its pair
+                // partner from stage R-1 of the previous step
+                const T vnew = gs(fq[h - 1], e, z);
+                const T vold = sp[slot(z)][row][2 * q + (e ^ 1)];
+                V out;
+                out.x = e ? vold : vnew;
+                out.y = e ? vnew : vold;
+                *reinterpret_cast<V*>(pout + (size_t)z * plane + (size_t)gj * nx + ia) = out;
+            }
         }
-        fprev = fcur;
     }
 }
 

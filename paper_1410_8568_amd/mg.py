@@ -21,7 +21,7 @@ MG_BC_NEUMANN = 0
 MG_MAX_LEVELS = 24
 MG_MAX_COARSE_CELLS = 512
 MG_MAX_HISTORY = 256
-MG_NUM_TILES = 8
+MG_NUM_TILES = 12
 KERNEL_CLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "refine", "other", "smooth_fine"]
 MG_K_COUNT = len(KERNEL_CLASSES)
 
