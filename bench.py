@@ -159,6 +159,111 @@ def summarize(d):
     print("\n".join(out))
 
 
+def batch_bench(args):
+    """64 uneven problems (sizes 32..128^3, 1-8 drops, ratio 10..1000): all submitted
+    at once to the continuous-batching server vs solved one after another."""
+    import torch
+    from paper_1410_8568_amd import inputs, mg
+    t = time.perf_counter()
+    probs = inputs.batch_problems(args.batch_count)
+    log(f"generated {len(probs)} batch problems in {time.perf_counter() - t:.1f} s")
+    dev = [mg.to_device(P) for P in probs]
+    cells = sum(P.cells for P in probs)
+    prec = "fp32_refined"
+    # warm the tuner cache for every size class
+    for n in sorted({P.n for P in probs}):
+        P = next(Q for Q in probs if Q.n == n)
+        mg.Solver(*mg.to_device(P)[:3], precision=prec).close()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    seq_cycles = 0
+    for (bx, by, bz, b) in dev:
+        S = mg.Solver(bx, by, bz, precision=prec)
+        p = torch.zeros_like(b)
+        st = S.solve(b, p, tol=args.tol)
+        seq_cycles += st["cycles"] * b.numel()
+        S.close()
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t
+    o = mg.options(precision=prec)
+    arena = sum(mg.workspace_bytes(P.n, o) for P in probs) + (1 << 20)
+    srv = mg.Server(arena, precision=prec, max_slots=args.slots)
+    outs = [torch.zeros_like(b) for (_, _, _, b) in dev]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    tickets = [srv.submit(bx, by, bz, b, p, tol=args.tol) for (bx, by, bz, b), p in zip(dev, outs)]
+    res = [srv.wait(tk) for tk in tickets]
+    srv_s = time.perf_counter() - t
+    srv.close()
+    bad = [r["rc"] for r in res if r["rc"] != 0]
+    lat = sorted(r["finish_ms"] - r["submit_ms"] for r in res)
+    out = {
+        "metric": "batched uneven solves: solves/s (FP32-refined, tol %g)" % args.tol,
+        "value": len(probs) / srv_s, "unit": "solves/s", "higher_is_better": True,
+        "n_gpus": 1, "data": "synthetic",
+        "config": {"workload": f"{len(probs)} problems n~U{{32,64,96,128}}, 1-8 drops, film 0.05-0.2, "
+                               f"ratio U{{10,100,1000}}, seeds 3 / 3000+i", "cells": cells,
+                   "slots": args.slots},
+        "server_s": srv_s, "sequential_s": seq_s, "speedup_vs_sequential": seq_s / srv_s,
+        "cell_updates_per_s": seq_cycles / srv_s, "failed": len(bad),
+        "latency_ms_p50": lat[len(lat) // 2], "latency_ms_max": lat[-1],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serve_bench(args):
+    """Open-loop Poisson arrivals of solves with n ~ U{64,128,192,256} and batch-like
+    geometry; p50/p99 latency (submit to finish) and achieved solves/s per rate."""
+    import numpy as np
+    import torch
+    from paper_1410_8568_amd import inputs, mg
+    prec = "fp32_refined"
+    rates = [float(r) for r in args.rates.split(",")]
+    # a pool of distinct fields per size class (requests reuse the pool's fields)
+    pool = {}
+    t = time.perf_counter()
+    for i, d in enumerate(inputs.request_stream(4 * args.pool, 1.0)):
+        if len(pool.setdefault(d[1]["n"], [])) < args.pool:
+            pool[d[1]["n"]].append(mg.to_device(inputs.problem_from_desc(d[1])))
+    log(f"generated request pool {[(n, len(v)) for n, v in sorted(pool.items())]} in {time.perf_counter() - t:.1f} s")
+    for n, v in pool.items():
+        mg.Solver(*v[0][:3], precision=prec).close()   # warm the tuner cache
+    o = mg.options(precision=prec)
+    arena = int(args.arena_gb * (1 << 30))
+    lines = []
+    for rate in rates:
+        stream = inputs.request_stream(args.requests, rate, seed=4)
+        srv = mg.Server(arena, precision=prec, max_slots=args.slots)
+        outs = {}
+        tickets = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, (ta, d) in enumerate(stream):
+            while time.perf_counter() - t0 < ta:
+                time.sleep(0.0001)
+            bx, by, bz, b = pool[d["n"]][i % len(pool[d["n"]])]
+            p = torch.zeros_like(b)
+            outs[i] = p
+            tickets.append((i, srv.submit(bx, by, bz, b, p, tol=args.tol)))
+        res = [srv.wait(tk, timeout_s=600) for _, tk in tickets]
+        span = time.perf_counter() - t0
+        srv.close()
+        lat = np.array([r["finish_ms"] - r["submit_ms"] for r in res])
+        line = {"rate_per_s": rate, "requests": len(res), "solves_per_s": len(res) / span,
+                "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+                "failed": int(sum(r["rc"] != 0 for r in res))}
+        log(json.dumps(line))
+        lines.append(line)
+    out = {"metric": "serving: p50/p99 latency and solves/s under Poisson arrivals (FP32-refined)",
+           "value": lines[-1]["solves_per_s"], "unit": "solves/s", "higher_is_better": True, "n_gpus": 1,
+           "data": "synthetic",
+           "config": {"workload": f"n~U{{64,128,192,256}}, batch-like geometry, {args.requests} requests per rate, "
+                                  f"pool of {args.pool} fields per size", "arena_gb": args.arena_gb,
+                      "slots": args.slots},
+           "rates": lines}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,12 +276,28 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (counter scale)")
     ap.add_argument("--summarize", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
+    ap.add_argument("--batch", action="store_true", help="batched uneven solves through the server")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--serve", action="store_true", help="Poisson-arrival serving sweep")
+    ap.add_argument("--rates", default="50,100,200,300,400,500")
+    ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--pool", type=int, default=2)
+    ap.add_argument("--arena-gb", type=float, default=24.0)
+    ap.add_argument("--slots", type=int, default=16)
     args = ap.parse_args()
     if args.summarize:
         summarize(args.summarize)
         return
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.batch or args.serve:
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        import torch
+        torch.cuda.set_device(0)
+        batch_bench(args) if args.batch else serve_bench(args)
         return
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "

@@ -74,7 +74,7 @@ typedef struct {
     int n_coarsest;  /* halve every dimension while all are even and the largest
                         exceeds n_coarsest (default 4); the coarsest grid must have
                         <= MG_MAX_COARSE_CELLS cells */
-    int inner_m;     /* FP32 V-cycles per FP64 outer iteration (refined mode, default 1) */
+    int inner_m;     /* FP32 V-cycles per FP64 outer iteration (refined mode, default 2) */
     int max_cycles;  /* V-cycles (FP64) or outer iterations (refined), default 100 */
     int profile;     /* nonzero: time every kernel launch with HIP events (stats.kernel_*) */
     int tile;        /* smoother kernel: 0 = automatic (each level's variant is chosen by
@@ -87,9 +87,10 @@ typedef struct {
 } mg_options;
 
 /* Fused sweep variants: variant v uses tile (v-1)/2 of the list 64x8, 128x4,
-   128x8, 64x16 (one sweep per pass), 64x4, 64x8 (two sweeps per pass), with a
-   target of about 1024 (v odd) or 4096 (v even) workgroups. */
-#define MG_NUM_TILES 12
+   128x8, 64x16 (one sweep per pass), 64x4, 64x8, 128x8, 64x16 (two sweeps per
+   pass), with a target of about 1024 (v odd) or 4096 (v even) workgroups.  The
+   last two two-sweep tiles exist in FP32 only; in FP64 they run as 64x8. */
+#define MG_NUM_TILES 16
 
 /* Kernel classes reported in mg_stats when options.profile is set. */
 enum {
@@ -191,8 +192,8 @@ typedef struct mg_server mg_server;
 
 typedef struct {
     mg_options solver;    /* options for every request (precision, sweeps, ...) */
-    int max_slots;        /* concurrent resident problems (default 16) */
-    void *stream;         /* hipStream_t the server launches on (NULL: default stream) */
+    int max_slots;        /* concurrent resident problems, 1..256; the server creates one
+                             HIP stream (default priority) per slot */
 } mg_server_options;
 
 typedef struct {
@@ -212,10 +213,14 @@ typedef struct {
 /*
  * Create a server that keeps each admitted request's hierarchy resident in
  * `arena` (caller-owned device memory of arena_bytes, 256-byte aligned; the HBM
- * budget).  A scheduler thread admits requests in arrival order as soon as their
- * workspace fits in the free part of the arena and a slot is free, and advances
- * every resident problem by one outer iteration per scheduling round; finished
- * problems release their memory at once.  Errors: MG_E_INVALID, MG_E_HIP.
+ * budget; it must outlive the server).  A scheduler thread admits requests in
+ * arrival order as soon as their workspace (mg_workspace_bytes) fits in the free
+ * part of the arena (first fit) and a slot is free, builds their hierarchy in
+ * place, and advances every resident problem one iteration (a V-cycle, or an
+ * outer refinement iteration) at a time on its slot's stream, relaunching each
+ * as soon as its previous iteration completes; finished problems release their
+ * memory at once, and waiting requests take their place.  The same request gives
+ * the same result alone or in any mix.  Errors: MG_E_INVALID, MG_E_HIP.
  */
 mg_status mg_server_create(void *arena, size_t arena_bytes, const mg_server_options *o,
                            mg_server **out);

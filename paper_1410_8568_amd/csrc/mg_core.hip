@@ -360,6 +360,13 @@ static void launch_sweep(hipStream_t s, const Lvl<T>& L, const T* pin, T* pout, 
 // Sweeps done by one pass of fused variant v (1..MG_NUM_TILES).
 static int sweeps_per_pass(int v) { return v > 8 ? 2 : 1; }
 
+// Variants 13..16 (two sweeps, 128x8 and 64x16 tiles) need more than 64 KiB of
+// LDS in FP64; there they fall back to the 64x8 two-sweep tile.
+template <class T>
+static bool variant_native(int v) {
+    return sizeof(T) == 4 || v <= 12;
+}
+
 // Fused sweep variant v in 1..MG_NUM_TILES: one pass doing sweeps_per_pass(v) sweeps.
 template <class T>
 static void fused_sweep(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0,
@@ -371,7 +378,19 @@ static void fused_sweep(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* 
         case 2: launch_sweep<T, 128, 8, 1>(s, L, pin, pout, b, c0, target, shift_sum); break;
         case 3: launch_sweep<T, 64, 16, 1>(s, L, pin, pout, b, c0, target, shift_sum); break;
         case 4: launch_sweep<T, 64, 4, 2>(s, L, pin, pout, b, c0, target, shift_sum); break;
-        default: launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum); break;
+        case 5: launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum); break;
+        case 6:
+            if constexpr (sizeof(T) == 4)
+                launch_sweep<T, 128, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum);
+            else
+                launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum);
+            break;
+        default:
+            if constexpr (sizeof(T) == 4)
+                launch_sweep<T, 64, 16, 2>(s, L, pin, pout, b, c0, target, shift_sum);
+            else
+                launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum);
+            break;
     }
 }
 
@@ -446,7 +465,7 @@ static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b
     float best = 1e30f;
     int bestv = -1;
     for (int v = -1; v <= MG_NUM_TILES; v++) {
-        if (v == 0) continue;
+        if (v == 0 || (v > 0 && !variant_native<T>(v))) continue;
         auto run = [&]() {
             if (v < 0)
                 ref_sweep<T>(s, L, pin, b, 0);
@@ -499,7 +518,7 @@ static bool smooth(mg_handle* h, Hier<T>& H, int l, int nsweep, int c0, T*& cur,
     if (tile > 0) {
         const int spp = sweeps_per_pass(tile);
         for (; rem >= spp; rem -= spp) {
-            Prof pf(h, cls, full);
+            Prof pf(h, cls, spp * full);   // algorithmic bytes: one sweep's worth per sweep done
             fused_sweep<T>(s, tile, H.L[l], cur, alt, H.rhs[l], c0, shifted ? nullptr : shift_sum);
             shifted = true;
             std::swap(cur, alt);
@@ -545,7 +564,7 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
     {
         Prof pf(h, MG_K_PROLONG, (2.0 * d.ncell() + 2.0 * c.ncell()) * sizeof(T));
         int nbp = 0;
-        const ColGrid G = zgrid(d.nx, d.ny, d.nz, false, &nbp);
+        const ColGrid G = zgrid(c.nx, d.ny, d.nz, false, &nbp);   // columns: coarse x by fine y
         k_prolong_col<T><<<nbp, CBX * CBY, 0, s>>>(H.e[l + 1], H.a[l + 1], c.nx, c.ny, c.nz, G, cur);
     }
     smooth(h, H, l, h->o.nu2, 1, cur, alt);
@@ -788,7 +807,7 @@ mg_status mg_default_options(mg_options* o) {
     o->nu1 = 2;
     o->nu2 = 2;
     o->n_coarsest = 4;
-    o->inner_m = 1;
+    o->inner_m = 2;
     o->max_cycles = 100;
     o->profile = 0;
     o->tile = 0;

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace mgk {
 
 constexpr int BX = 64;   // threads along i (one wavefront)
@@ -423,6 +425,16 @@ __device__ __forceinline__ int xcd_tile(int w, int nwg) {
     return x * q + min(x, r) + m;
 }
 
+// Compile-time loop: f(std::integral_constant<int, i>) for i = B .. E-1, so that
+// arrays indexed by i are only ever indexed by constants (and stay in registers).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
 template <class T>
 struct Vec2;
 template <>
@@ -482,70 +494,79 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
     const size_t plane = (size_t)nx * ny;
     const T shift = shift_sum ? (T)(shift_sum[0] / n_cells) : T(0);
 
-    long roff[NP];
-    int rpos[NP];
+    // Global loads are unconditional (clamped to a valid address) so the compiler
+    // can leave them in flight until first use; out-of-grid values are zeroed
+    // where they are written to LDS or consumed.
+    long roff[NP];    // offset of staged pair u within a plane, clamped
+    int rpos[NP];     // its LDS position (-1: no pair u for this thread)
+    bool rin[NP];     // inside the grid
 #pragma unroll
     for (int u = 0; u < NP; u++) {
         const int v = tid + u * NT;
         const int vi = v % (W / 2), vj = v / (W / 2);
         const int ii = i0 - R + 2 * vi, jj = j0 - R + vj;
         rpos[u] = v < NV ? vj * W + 2 * vi : -1;
-        roff[u] = (v < NV && ii >= 0 && ii < nx && jj >= 0 && jj < ny) ? (long)jj * nx + ii : -1;
+        rin[u] = v < NV && ii >= 0 && ii < nx && jj >= 0 && jj < ny;
+        roff[u] = rin[u] ? (long)jj * nx + ii : 0;
     }
     T* const spf = &sp[0][0][0];
     auto slot = [](int k) { return (k + 4 * NS) % NS; };
+    auto kclamp = [&](int k) { return k < 0 ? 0 : (k >= nz ? nz - 1 : k); };
     auto fetch_ring = [&](int k, V* v) {
-        const bool kin = k >= 0 && k < nz;
+        const size_t base = (size_t)kclamp(k) * plane;
 #pragma unroll
-        for (int u = 0; u < NP; u++) {
-            V x;
-            x.x = T(0);
-            x.y = T(0);
-            if (kin && roff[u] >= 0) {
-                x = *reinterpret_cast<const V*>(pin + (size_t)k * plane + roff[u]);
-                x.x -= shift;
-                x.y -= shift;
-            }
-            v[u] = x;
-        }
+        for (int u = 0; u < NP; u++) v[u] = *reinterpret_cast<const V*>(pin + base + roff[u]);
     };
     auto store_ring = [&](int k, const V* v) {
         T* dst = spf + slot(k) * (H * W);
+        const bool kin = k >= 0 && k < nz;
 #pragma unroll
         for (int u = 0; u < NP; u++)
-            if (rpos[u] >= 0) *reinterpret_cast<V*>(dst + rpos[u]) = v[u];
+            if (rpos[u] >= 0) {
+                V x;
+                const bool ok = kin && rin[u];
+                x.x = ok ? v[u].x - shift : T(0);
+                x.y = ok ? v[u].y - shift : T(0);
+                *reinterpret_cast<V*>(dst + rpos[u]) = x;
+            }
     };
-    // face coefficients and right-hand side of the pair on one plane
+    // face coefficients and right-hand side of the pair on one plane; the upper
+    // faces past the last cell (wall) are masked where they are used
     struct FB {
         V fx, fy, fyu, fz, fzu, bb;
-        T fxu;  // upper x-face of the second cell
+        T fxu;   // upper x-face of the second cell
     };
+    const bool xu = ia + 2 < nx, yu = gj + 1 < ny;
+    const size_t col = inpair ? (size_t)gj * nx + ia : 0;
+    // Offsets of the upper faces (0 at a wall, where the value is masked).  They
+    // pass through an empty asm so the compiler cannot see that they may equal
+    // another load's address and fold the loads into a copy (a copy would have
+    // to wait for the load right away).
+    int xo = xu ? 2 : 0, yo = yu ? nx : 0;
+    asm volatile("" : "+v"(xo), "+v"(yo));
     auto fetch_fb = [&](int k) {
         FB f;
-        const V z2{T(0), T(0)};
-        f.fx = f.fy = f.fyu = f.fz = f.fzu = f.bb = z2;
-        f.fxu = T(0);
-        if (inpair && k >= 0 && k < nz) {
-            const size_t c = (size_t)k * plane + (size_t)gj * nx + ia;
-            f.fx = *reinterpret_cast<const V*>(L.fx + c);
-            if (ia + 2 < nx) f.fxu = L.fx[c + 2];
-            f.fy = *reinterpret_cast<const V*>(L.fy + c);
-            if (gj + 1 < ny) f.fyu = *reinterpret_cast<const V*>(L.fy + c + nx);
-            f.fz = *reinterpret_cast<const V*>(L.fz + c);
-            if (k + 1 < nz) f.fzu = *reinterpret_cast<const V*>(L.fz + c + plane);
-            f.bb = *reinterpret_cast<const V*>(b + c);
-        }
+        const int kk = kclamp(k);
+        const size_t c = (size_t)kk * plane + col;
+        const size_t zo = kk + 1 < nz ? plane : 0;   // uniform: no copy of another load
+        f.fx = *reinterpret_cast<const V*>(L.fx + c);
+        f.fxu = L.fx[c + xo];
+        f.fy = *reinterpret_cast<const V*>(L.fy + c);
+        f.fyu = *reinterpret_cast<const V*>(L.fy + c + yo);
+        f.fz = *reinterpret_cast<const V*>(L.fz + c);
+        f.fzu = *reinterpret_cast<const V*>(L.fz + c + zo);
+        f.bb = *reinterpret_cast<const V*>(b + c);
         return f;
     };
     // Gauss-Seidel value of cell e (0: first of the pair) on plane k with faces f.
     auto gs = [&](const FB& f, int e, int k) {
         const int col = 2 * q + e;
         const T w0 = e ? f.fx.y : f.fx.x;
-        const T w1 = e ? f.fxu : f.fx.y;
+        const T w1 = e ? (xu ? f.fxu : T(0)) : f.fx.y;
         const T w2 = e ? f.fy.y : f.fy.x;
-        const T w3 = e ? f.fyu.y : f.fyu.x;
+        const T w3 = yu ? (e ? f.fyu.y : f.fyu.x) : T(0);
         const T w4 = e ? f.fz.y : f.fz.x;
-        const T w5 = e ? f.fzu.y : f.fzu.x;
+        const T w5 = k + 1 < nz ? (e ? f.fzu.y : f.fzu.x) : T(0);
         const T bb = e ? f.bb.y : f.bb.x;
         T(*c)[W] = sp[slot(k)];
         const T s = stencil_sum(w0, w1, w2, w3, w4, w5, c[row][col - 1], c[row][col + 1], c[row - 1][col],
@@ -562,27 +583,28 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
     fetch_ring(tfirst + 1, ring);
     FB fq[R];                 // fq[h-1]: faces of plane t-h+1 during step t
     FB fnext = fetch_fb(tfirst);
-#pragma unroll
-    for (int h = 0; h < R; h++) fq[h] = fnext;
+    static_for<0, R>([&](auto hc) { fq[decltype(hc)::value] = fnext; });
     for (int t = tfirst; t <= tlast; t++) {
         store_ring(t + 1, ring);
-#pragma unroll
-        for (int h = R - 1; h > 0; h--) fq[h] = fq[h - 1];
+        static_for<1, R>([&](auto hc) {
+            constexpr int h = R - decltype(hc)::value;   // R-1 down to 1
+            fq[h] = fq[h - 1];
+        });
         fq[0] = fnext;
         lds_barrier();
-        fetch_ring(t + 2, ring);
+        fetch_ring(t + 2, ring);     // in flight during this step
         fnext = fetch_fb(t + 1);
         // the cell of the pair that stage 1 updates on plane t; every stage of
         // this step updates the same cell (on its own plane)
         const int e = (c0 + i0 + gj + t) & 1;
         const int col = 2 * q + e;
-#pragma unroll
-        for (int h = 1; h <= R; h++) {
+        static_for<1, R + 1>([&](auto hc) {
+            constexpr int h = decltype(hc)::value;
             const int z = t - h + 1;       // this stage's plane
-            const int rg = R - h;          // this stage's ring width
+            constexpr int rg = R - h;      // this stage's ring width
             const bool in_ring = col >= R - rg && col < R + TX + rg && row >= R - rg && row < R + TY + rg;
             const bool in_z = z >= 0 && z < nz && z >= k0 - rg && z < k1 + rg;
-            if (h < R) {
+            if constexpr (h < R) {
                 if (inpair && in_ring && in_z) sp[slot(z)][row][col] = gs(fq[h - 1], e, z);
                 lds_barrier();
             } else if (inpair && in_ring && in_z) {
@@ -595,7 +617,7 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
                 out.y = e ? vnew : vold;
                 *reinterpret_cast<V*>(pout + (size_t)z * plane + (size_t)gj * nx + ia) = out;
             }
-        }
+        });
     }
 }
 
@@ -739,45 +761,58 @@ __global__ void __launch_bounds__(256) k_resid_restrict_col(Lvl<T> L, const T* _
     }
 }
 
-// Flux-conserving prolongation and correction, z-marching: thread (i, j) owns
-// one fine column.  Its octant side in x and y is fixed, so the coarse cells it
-// needs are the 2 x 2 columns (I or Ix) x (J or Jy); along z it keeps three
-// coarse planes (a and a*e) in registers and advances one coarse plane every
-// two fine planes.  V_T = sum a e / sum a over the corner's cells; the corner
-// T = {} is the coarse cell itself, V = e_C.
+// Flux-conserving prolongation and correction, z-marching.  Thread (I, j) owns
+// the fine cell pair i = 2I, 2I+1 of fine row j: both are children of coarse
+// column I with the same y side (Jy) and opposite x sides (I-1 for the even
+// child, I+1 for the odd one, clamped = wall mirror).  The thread keeps three
+// coarse planes of a and a*e for the 3 x 2 coarse columns it needs in registers
+// and advances one coarse plane every two fine planes.  For each child, corner
+// T of its octant has V_T = sum a e / sum a over the 2^|T| coarse cells sharing
+// it (T = {} is the coarse cell itself, V = e_C); the child gets
+// (1/8) * sum_T V_T, the corners summed in the order {}, x, y, xy, z, xz, yz, xyz
+// and the cells of a corner with x fastest, then y, then z.  The corners y, z,
+// yz are shared by the two children.  The next fine plane's pair is loaded one
+// step ahead.  Requires even fine nx (always: fine = 2 * coarse).
 template <class T>
 __global__ void __launch_bounds__(CBX* CBY) k_prolong_col(const T* __restrict__ ec, const T* __restrict__ ac,
                                                          int cnx, int cny, int cnz, ColGrid G, T* __restrict__ ef) {
+    using V = typename Vec2<T>::type;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
     const int nx = 2 * cnx, ny = 2 * cny, nz = 2 * cnz;
-    const int i = tx * CBX + (int)(threadIdx.x % CBX), j = ty * CBY + (int)(threadIdx.x / CBX);
+    const int I = tx * CBX + (int)(threadIdx.x % CBX), j = ty * CBY + (int)(threadIdx.x / CBX);
     const int k0 = chunk * G.kc, k1 = min(nz, k0 + G.kc);
-    if (i >= nx || j >= ny || k0 >= k1) return;
-    const int I = i >> 1, J = j >> 1;
-    const int Ix = (i & 1) ? min(I + 1, cnx - 1) : max(I - 1, 0);
+    if (I >= cnx || j >= ny || k0 >= k1) return;
+    const int J = j >> 1;
+    const int Im = max(I - 1, 0), Ip = min(I + 1, cnx - 1);
     const int Jy = (j & 1) ? min(J + 1, cny - 1) : max(J - 1, 0);
     const size_t cplane = (size_t)cnx * cny;
-    const size_t o00 = (size_t)J * cnx + I, o10 = (size_t)J * cnx + Ix, o01 = (size_t)Jy * cnx + I,
-                 o11 = (size_t)Jy * cnx + Ix;
-    // coarse plane K: a[4], w[4] = a*e for cells (I,J), (Ix,J), (I,Jy), (Ix,Jy)
+    const size_t rJ = (size_t)J * cnx, rY = (size_t)Jy * cnx;
+    // one coarse plane: (a, w = a*e) at columns (x0 = I, xm = Im, xp = Ip) x (J, Jy)
     struct CP {
-        T a0, a1, a2, a3, w0, w1, w2, w3, e0;
+        T a0, am, ap, ay0, aym, ayp;
+        T w0, wm, wp, wy0, wym, wyp;
+        T e0;
     };
     auto load = [&](int K) {
         CP c;
         const size_t base = (size_t)K * cplane;
-        c.a0 = ac[base + o00]; c.a1 = ac[base + o10]; c.a2 = ac[base + o01]; c.a3 = ac[base + o11];
-        c.e0 = ec[base + o00];
+        c.a0 = ac[base + rJ + I]; c.am = ac[base + rJ + Im]; c.ap = ac[base + rJ + Ip];
+        c.ay0 = ac[base + rY + I]; c.aym = ac[base + rY + Im]; c.ayp = ac[base + rY + Ip];
+        c.e0 = ec[base + rJ + I];
         c.w0 = c.a0 * c.e0;
-        c.w1 = c.a1 * ec[base + o10];
-        c.w2 = c.a2 * ec[base + o01];
-        c.w3 = c.a3 * ec[base + o11];
+        c.wm = c.am * ec[base + rJ + Im];
+        c.wp = c.ap * ec[base + rJ + Ip];
+        c.wy0 = c.ay0 * ec[base + rY + I];
+        c.wym = c.aym * ec[base + rY + Im];
+        c.wyp = c.ayp * ec[base + rY + Ip];
         return c;
     };
     int Kc = k0 >> 1;
     CP cm = load(max(Kc - 1, 0)), c0 = load(Kc), cp = load(min(Kc + 1, cnz - 1));
     const size_t fplane = (size_t)nx * ny;
+    const size_t fcol = (size_t)j * nx + 2 * I;
+    V fnext = *reinterpret_cast<const V*>(ef + (size_t)k0 * fplane + fcol);
     for (int k = k0; k < k1; k++) {
         const int K = k >> 1;
         if (K != Kc) {
@@ -786,19 +821,35 @@ __global__ void __launch_bounds__(CBX* CBY) k_prolong_col(const T* __restrict__ 
             c0 = cp;
             cp = load(min(K + 1, cnz - 1));
         }
-        const CP& cz = (k & 1) ? cp : cm;   // the coarse plane on this child's z side
-        // corners: {}, {x}, {y}, {x,y}, then the same with z
-        T tot = c0.e0;
-        tot += (c0.w0 + c0.w1) / (c0.a0 + c0.a1);
-        tot += (c0.w0 + c0.w2) / (c0.a0 + c0.a2);
-        tot += (((c0.w0 + c0.w1) + c0.w2) + c0.w3) / (((c0.a0 + c0.a1) + c0.a2) + c0.a3);
-        tot += (c0.w0 + cz.w0) / (c0.a0 + cz.a0);
-        tot += (((c0.w0 + c0.w1) + cz.w0) + cz.w1) / (((c0.a0 + c0.a1) + cz.a0) + cz.a1);
-        tot += (((c0.w0 + c0.w2) + cz.w0) + cz.w2) / (((c0.a0 + c0.a2) + cz.a0) + cz.a2);
-        tot += (((((((c0.w0 + c0.w1) + c0.w2) + c0.w3) + cz.w0) + cz.w1) + cz.w2) + cz.w3) /
-               (((((((c0.a0 + c0.a1) + c0.a2) + c0.a3) + cz.a0) + cz.a1) + cz.a2) + cz.a3);
-        const size_t f = (size_t)k * fplane + (size_t)j * nx + i;
-        ef[f] += tot / T(8);
+        V f = fnext;
+        if (k + 1 < k1) fnext = *reinterpret_cast<const V*>(ef + (size_t)(k + 1) * fplane + fcol);
+        const CP& cz = (k & 1) ? cp : cm;   // the coarse plane on these children's z side
+        // shared corners
+        const T vy = (c0.w0 + c0.wy0) / (c0.a0 + c0.ay0);
+        const T vz = (c0.w0 + cz.w0) / (c0.a0 + cz.a0);
+        const T vyz = (((c0.w0 + c0.wy0) + cz.w0) + cz.wy0) / (((c0.a0 + c0.ay0) + cz.a0) + cz.ay0);
+        // child 0 (x side Im), child 1 (x side Ip)
+        T tot[2];
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+            const T ax = e ? c0.ap : c0.am, wx = e ? c0.wp : c0.wm;
+            const T axy = e ? c0.ayp : c0.aym, wxy = e ? c0.wyp : c0.wym;
+            const T azx = e ? cz.ap : cz.am, wzx = e ? cz.wp : cz.wm;
+            const T azxy = e ? cz.ayp : cz.aym, wzxy = e ? cz.wyp : cz.wym;
+            T t = c0.e0;
+            t += (c0.w0 + wx) / (c0.a0 + ax);
+            t += vy;
+            t += (((c0.w0 + wx) + c0.wy0) + wxy) / (((c0.a0 + ax) + c0.ay0) + axy);
+            t += vz;
+            t += (((c0.w0 + wx) + cz.w0) + wzx) / (((c0.a0 + ax) + cz.a0) + azx);
+            t += vyz;
+            t += (((((((c0.w0 + wx) + c0.wy0) + wxy) + cz.w0) + wzx) + cz.wy0) + wzxy) /
+                 (((((((c0.a0 + ax) + c0.ay0) + axy) + cz.a0) + azx) + cz.ay0) + azxy);
+            tot[e] = t;
+        }
+        f.x += tot[0] / T(8);
+        f.y += tot[1] / T(8);
+        *reinterpret_cast<V*>(ef + (size_t)k * fplane + fcol) = f;
     }
 }
 

@@ -22,56 +22,12 @@
 #include <unordered_map>
 #include <vector>
 
+#include "mg_arena.h"
 #include "mg_core.h"
 
 using namespace mgrt;
 
 namespace {
-
-// First-fit allocator over [0, size) with coalescing frees.
-class Arena {
-   public:
-    void reset(size_t size) {
-        free_.clear();
-        if (size) free_[0] = size;
-    }
-    bool alloc(size_t bytes, size_t* off) {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                size_t rest = it->second - bytes;
-                size_t at = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[at] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t free_bytes() const {
-        size_t s = 0;
-        for (auto& kv : free_) s += kv.second;
-        return s;
-    }
-
-   private:
-    std::map<size_t, size_t> free_;
-};
 
 enum JobState { QUEUED, RUNNING, DONE };
 
@@ -101,7 +57,7 @@ struct mg_server {
     std::vector<hipStream_t> streams;
     std::vector<int> slot_free;
     std::vector<hipEvent_t> events;
-    Arena alloc;
+    mgrt::Arena alloc;
     std::thread th;
     bool stop = false;
     uint64_t next_ticket = 1;

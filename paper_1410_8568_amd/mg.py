@@ -21,7 +21,7 @@ MG_BC_NEUMANN = 0
 MG_MAX_LEVELS = 24
 MG_MAX_COARSE_CELLS = 512
 MG_MAX_HISTORY = 256
-MG_NUM_TILES = 12
+MG_NUM_TILES = 16
 KERNEL_CLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "refine", "other", "smooth_fine"]
 MG_K_COUNT = len(KERNEL_CLASSES)
 
@@ -66,7 +66,7 @@ class Stats(ctypes.Structure):
 
 
 class ServerOptions(ctypes.Structure):
-    _fields_ = [("solver", Options), ("max_slots", ctypes.c_int), ("stream", ctypes.c_void_p)]
+    _fields_ = [("solver", Options), ("max_slots", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):
@@ -127,7 +127,7 @@ class MGError(RuntimeError):
         self.status = status
 
 
-def options(precision="fp64", nu1=2, nu2=2, n_coarsest=4, inner_m=1, max_cycles=100, profile=False,
+def options(precision="fp64", nu1=2, nu2=2, n_coarsest=4, inner_m=2, max_cycles=100, profile=False,
             tile=0):
     o = Options()
     lib().mg_default_options(ctypes.byref(o))
@@ -241,6 +241,77 @@ class Solver:
     def close(self):
         if getattr(self, "h", None):
             lib().mg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching solve server over a torch uint8 arena (the HBM budget).
+
+    ``submit`` queues a solve and returns a ticket; the caller keeps the request's
+    tensors alive until ``poll`` returns a result (the binding holds references)."""
+
+    def __init__(self, arena_bytes, precision="fp64", max_slots=16, device="cuda", **kw):
+        import torch
+        self.arena = torch.empty(arena_bytes + 256, dtype=torch.uint8, device=device)
+        self._arena_ptr = (self.arena.data_ptr() + 255) & ~255
+        self.opts = ServerOptions(options(precision=precision, **kw), max_slots)
+        h = ctypes.c_void_p()
+        st = lib().mg_server_create(ctypes.c_void_p(self._arena_ptr), ctypes.c_size_t(arena_bytes),
+                                    ctypes.byref(self.opts), ctypes.byref(h))
+        if st != MG_OK:
+            raise MGError(st, "mg_server_create")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, bx, by, bz, b, p, tol=1e-10):
+        nz, ny, nxp = bx.shape
+        n = (nxp - 1, ny, nz)
+        nx = n[0]
+        _check_field(bx, (nz, ny, nx + 1), "bx")
+        _check_field(by, (nz, ny + 1, nx), "by")
+        _check_field(bz, (nz + 1, ny, nx), "bz")
+        _check_field(b, (nz, ny, nx), "b")
+        _check_field(p, (nz, ny, nx), "p")
+        r = Request(Grid(*n), bx.data_ptr(), by.data_ptr(), bz.data_ptr(), b.data_ptr(), p.data_ptr(), tol)
+        t = ctypes.c_uint64()
+        st = lib().mg_batch_submit(self.h, ctypes.byref(r), ctypes.byref(t))
+        if st != MG_OK:
+            raise MGError(st, "mg_batch_submit")
+        self._keep[t.value] = (bx, by, bz, b, p)
+        return t.value
+
+    def poll(self, ticket):
+        """None while pending, else dict(rc, stats, submit_ms, start_ms, finish_ms)."""
+        res = Result()
+        st = lib().mg_poll(self.h, ctypes.c_uint64(ticket), ctypes.byref(res))
+        if st == MG_PENDING:
+            return None
+        if st == MG_E_NOT_FOUND:
+            raise MGError(st, "mg_poll")
+        self._keep.pop(ticket, None)
+        return dict(rc=st, stats=res.stats.to_dict(), submit_ms=res.submit_ms, start_ms=res.start_ms,
+                    finish_ms=res.finish_ms)
+
+    def wait(self, ticket, timeout_s=120.0):
+        import time
+        t0 = time.time()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.time() - t0 > timeout_s:
+                raise TimeoutError(f"ticket {ticket} not finished after {timeout_s} s")
+            time.sleep(0.0002)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mg_server_destroy(self.h)
             self.h = None
 
     def __del__(self):
