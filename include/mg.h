@@ -84,6 +84,10 @@ typedef struct {
                         one-colour-per-pass kernels on every level, 1..MG_NUM_TILES = one fixed
                         variant of the fused red-black sweep on every level that has a
                         ping-pong buffer.  Every choice gives bit-identical results. */
+    int graph;       /* nonzero: capture one iteration's launches into a hipGraph on the first
+                        iteration of a solve and replay it for the others (fewer host launches;
+                        identical results).  Ignored when profile is set.  The server always
+                        uses graphs. */
 } mg_options;
 
 /* Fused sweep variants: variant v uses tile (v-1)/2 of the list 64x8, 128x4,

@@ -103,6 +103,9 @@ struct SolveState {
     int it = 0;
     int status = MG_OK;
     bool project = false;  // p still needs its final mean-zero projection
+    hipGraph_t graph = nullptr;          // one captured iteration (options.graph)
+    hipGraphExec_t gexec = nullptr;
+    bool graph_failed = false;
     std::chrono::steady_clock::time_point t0;
 };
 mg_status solve_begin(SolveState& S);             // blocking: projection + initial residual
@@ -110,4 +113,5 @@ mg_status solve_launch_iteration(SolveState& S);  // asynchronous: one (outer) i
 void solve_after_sync(SolveState& S);             // after h->stream is synchronised
 bool solve_running(const SolveState& S);
 void solve_end(SolveState& S, mg_stats* st);
+void solve_release(SolveState& S);                // frees the captured graph (error paths)
 }  // namespace mgrt

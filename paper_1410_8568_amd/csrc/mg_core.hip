@@ -574,11 +574,6 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
     }
 }
 
-static double pow2_near(double v) {
-    if (!(v > 0) || !std::isfinite(v)) return 1.0;
-    return std::ldexp(1.0, (int)std::floor(std::log2(v)));
-}
-
 // Run partial-sum kernel output through k_finish2 into scal[slot], scal[slot+1].
 static void finish(mg_handle* h, int nblk, int slot) {
     Prof pf(h, MG_K_OTHER, 16.0 * nblk);
@@ -647,15 +642,16 @@ mg_status solve_begin(SolveState& S) {
         return MG_OK;
     }
     const double resid_bytes = (2.0 * N + d0.nfaces()) * 8.0;
-    S.scale = pow2_near(S.norm_b / std::sqrt(N));
     int nbz = 0;
     const ColGrid G0 = zgrid(d0.nx, d0.ny, d0.nz, false, &nbz);
     if (f32) {
+        // first FP32 right-hand side scaled by a power of two near the RMS of b_bar
+        k_refine_scale<<<1, 64, 0, s>>>(h->scal + 3, N, h->scal + 8);
         Prof pf(h, MG_K_REFINE, resid_bytes + 4.0 * N);
-        k_resid_col<double, 1><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, 1.0 / S.scale, h->frhs[0], h->part);
+        k_resid_col<double, 1><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, h->scal + 9, h->frhs[0], h->part);
     } else {
         Prof pf(h, MG_K_NORM, resid_bytes);
-        k_resid_col<double, 0><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, 1.0, nullptr, h->part);
+        k_resid_col<double, 0><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, nullptr, nullptr, h->part);
     }
     finish(h, nbz, 4);
     S.project = true;  // scal[5] now holds sum(p); p is made mean-zero lazily
@@ -676,7 +672,7 @@ mg_status solve_begin(SolveState& S) {
 // that rewrites p (the first fused pre-smoothing sweep, or the refinement
 // update) and, after the last iteration, done by solve_end.  The caller
 // synchronises h->stream before solve_after_sync.
-mg_status solve_launch_iteration(SolveState& S) {
+static mg_status launch_iteration_kernels(SolveState& S) {
     mg_handle* h = S.h;
     const LevelDims& d0 = h->L.d[0];
     const double N = (double)d0.ncell();
@@ -698,30 +694,62 @@ mg_status solve_launch_iteration(SolveState& S) {
             shift = nullptr;
         }
         vcycle(h, H64, 0, shift);
-        S.st.cycles++;
         Prof pf(h, MG_K_NORM, resid_bytes);
-        k_resid_col<double, 0><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, 1.0, nullptr, h->part);
+        k_resid_col<double, 0><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, nullptr, nullptr, h->part);
     } else {
         {
             Prof pf(h, MG_K_OTHER, 4.0 * N);
             k_fill<float><<<lin_grid(d0.ncell()), 256, 0, s>>>(h->fe[0], d0.ncell(), 0.0f);
         }
-        for (int m = 0; m < h->o.inner_m; m++) {
-            vcycle(h, H32, 0);
-            S.st.cycles++;
-        }
+        for (int m = 0; m < h->o.inner_m; m++) vcycle(h, H32, 0);
         {
             Prof pf(h, MG_K_REFINE, 20.0 * N);
-            k_refine_update<<<lin_grid(d0.ncell()), 256, 0, s>>>(S.p, h->fe[0], S.scale, d0.ncell(), h->scal + 5);
+            k_refine_update<<<lin_grid(d0.ncell()), 256, 0, s>>>(S.p, h->fe[0], h->scal + 8, d0.ncell(), h->scal + 5);
         }
-        // r32 of the next iteration is scaled by a power of two near the RMS of the
+        // r32 of the next step is scaled by a power of two near the RMS of the
         // residual just used (any power of two leaves the FP32 arithmetic unchanged)
-        S.scale = pow2_near(S.rho * S.norm_b / std::sqrt(N));
+        k_refine_scale<<<1, 64, 0, s>>>(h->scal + 4, N, h->scal + 8);
         Prof pf(h, MG_K_REFINE, resid_bytes + 4.0 * N);
-        k_resid_col<double, 1><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, 1.0 / S.scale, h->frhs[0], h->part);
+        k_resid_col<double, 1><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, h->scal + 9, h->frhs[0], h->part);
     }
     finish(h, nbz, 4);
     HIPCHK(hipGetLastError());
+    return MG_OK;
+}
+
+mg_status solve_launch_iteration(SolveState& S) {
+    mg_handle* h = S.h;
+    hipStream_t s = h->stream;
+    if (h->o.graph && !h->o.profile && !S.graph_failed) {
+        if (!S.gexec) {
+            // record this iteration's launches once; on any failure fall back to eager launches
+            bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                const mg_status r = launch_iteration_kernels(S);
+                hipGraph_t g = nullptr;
+                const bool ended = hipStreamEndCapture(s, &g) == hipSuccess;
+                ok = r == MG_OK && ended && g != nullptr;
+                if (ok) {
+                    S.graph = g;
+                    ok = hipGraphInstantiate(&S.gexec, g, nullptr, nullptr, 0) == hipSuccess;
+                } else if (g) {
+                    (void)hipGraphDestroy(g);
+                }
+            }
+            if (!ok) {
+                (void)hipGetLastError();
+                S.graph_failed = true;
+                S.gexec = nullptr;
+            }
+        }
+        if (S.gexec) {
+            HIPCHK(hipGraphLaunch(S.gexec, s));
+            HIPCHK(hipMemcpyAsync(h->host, h->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            return MG_OK;
+        }
+    }
+    const mg_status r = launch_iteration_kernels(S);
+    if (r != MG_OK) return r;
     HIPCHK(hipMemcpyAsync(h->host, h->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     return MG_OK;
 }
@@ -729,6 +757,7 @@ mg_status solve_launch_iteration(SolveState& S) {
 // Step 3 (after the stream is synchronised): record the residual, test convergence.
 void solve_after_sync(SolveState& S) {
     S.it++;
+    S.st.cycles += S.h->o.precision == MG_FP32_REFINED ? S.h->o.inner_m : 1;
     S.rho = std::sqrt(S.h->host[0]) / S.norm_b;
     if (S.st.nhist < MG_MAX_HISTORY) S.st.history[S.st.nhist++] = S.rho;
     if (!(S.rho == S.rho) || S.rho > 1e6 * S.rho0)
@@ -743,6 +772,14 @@ bool solve_running(const SolveState& S) {
     return S.status == MG_E_NOT_CONVERGED && S.it < S.h->o.max_cycles;
 }
 
+// Release the captured iteration graph, if any.
+void solve_release(SolveState& S) {
+    if (S.gexec) (void)hipGraphExecDestroy(S.gexec);
+    if (S.graph) (void)hipGraphDestroy(S.graph);
+    S.gexec = nullptr;
+    S.graph = nullptr;
+}
+
 // Step 4: final mean-zero projection of p (sum(p) from the last residual pass),
 // then statistics.  Blocking.
 void solve_end(SolveState& S, mg_stats* st) {
@@ -755,6 +792,7 @@ void solve_end(SolveState& S, mg_stats* st) {
         S.project = false;
     }
     (void)hipStreamSynchronize(h->stream);
+    solve_release(S);
     S.st.outer = S.it;
     if (h->o.precision == MG_FP64) S.st.cycles = S.it;
     S.st.rel_residual = S.rho;
@@ -780,11 +818,16 @@ mg_status solve_impl(mg_handle* h, const double* rhs, double* p, double tol, mg_
     if (r != MG_OK) return r;
     while (solve_running(S)) {
         r = solve_launch_iteration(S);
-        if (r != MG_OK) return r;
-        HIPCHK(hipStreamSynchronize(h->stream));
+        if (r == MG_OK && hipStreamSynchronize(h->stream) != hipSuccess) {
+            set_error("hipStreamSynchronize failed during the solve");
+            r = MG_E_HIP;
+        }
+        if (r != MG_OK) {
+            solve_release(S);
+            return r;
+        }
         solve_after_sync(S);
     }
-    HIPCHK(hipStreamSynchronize(h->stream));
     solve_end(S, st);
     if (S.status == MG_E_NOT_CONVERGED) set_error("max_cycles reached before the tolerance");
     if (S.status == MG_E_DIVERGED) set_error("residual diverged");
@@ -811,6 +854,7 @@ mg_status mg_default_options(mg_options* o) {
     o->max_cycles = 100;
     o->profile = 0;
     o->tile = 0;
+    o->graph = 0;
     return MG_OK;
 }
 

@@ -199,6 +199,20 @@ __global__ void k_cast_d2f(const double* __restrict__ x, float* __restrict__ y, 
     for (; t < n; t += (size_t)gridDim.x * blockDim.x) y[t] = (float)x[t];
 }
 
+// Scale of the FP32 right-hand side of the next refinement step: the power of
+// two at or below the RMS of the residual whose sum of squares is sumsq[0]
+// (1 for a zero residual); out[0] = s, out[1] = 1/s (both exact).  Any power of
+// two gives the same FP32 arithmetic up to that scale.
+__global__ void k_refine_scale(const double* __restrict__ sumsq, double n, double* __restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double rms = sqrt(sumsq[0] / n);
+        double s = 1.0;
+        if (rms > 0.0 && rms < 1e300) s = ldexp(1.0, ilogb(rms));
+        out[0] = s;
+        out[1] = 1.0 / s;
+    }
+}
+
 // ---------------------------------------------------------------- setup
 
 // Caller faces (x: [nz][ny][nx+1], y: [nz][ny+1][nx], z: [nz+1][ny][nx]) to
@@ -660,17 +674,18 @@ __device__ __forceinline__ Plane1<T> load_plane1(const Lvl<T>& L, const T* __res
 }
 
 // Residual r = b - L p along each column; MODE 0: partial sums of r^2 and p;
-// MODE 1 (FP64 refinement): also writes r32 = float(r * inv_s).
+// MODE 1 (FP64 refinement): also writes r32 = float(r * scal_inv_s[0]).
 template <class T, int MODE>
 __global__ void __launch_bounds__(CBX* CBY) k_resid_col(Lvl<T> L, const T* __restrict__ p, const T* __restrict__ b,
-                                                       ColGrid G, double inv_s, float* __restrict__ r32,
-                                                       double* __restrict__ part) {
+                                                       ColGrid G, const double* __restrict__ scal_inv_s,
+                                                       float* __restrict__ r32, double* __restrict__ part) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
     const int i = tx * CBX + (int)(threadIdx.x % CBX), j = ty * CBY + (int)(threadIdx.x / CBX);
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int k0 = chunk * G.kc, k1 = min(nz, k0 + G.kc);
     double a = 0, q = 0;
+    const double inv_s = MODE == 1 ? scal_inv_s[0] : 1.0;
     if (i < nx && j < ny && k0 < k1) {
         const size_t plane = (size_t)nx * ny;
         const size_t col = (size_t)j * nx + i;
@@ -854,10 +869,12 @@ __global__ void __launch_bounds__(CBX* CBY) k_prolong_col(const T* __restrict__ 
 }
 
 // FP64 update p = (p - mean) + s * e32, the mean being shift_sum[0] / N (the
-// mean-zero projection of the previous iterate, folded into this pass).
-__global__ void k_refine_update(double* __restrict__ p, const float* __restrict__ e, double s, size_t n,
-                                const double* __restrict__ shift_sum) {
+// mean-zero projection of the previous iterate, folded into this pass) and s
+// = scal_s[0] the scale the residual was divided by.
+__global__ void k_refine_update(double* __restrict__ p, const float* __restrict__ e, const double* __restrict__ scal_s,
+                                size_t n, const double* __restrict__ shift_sum) {
     const double c = shift_sum[0] / (double)n;
+    const double s = scal_s[0];
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
         p[t] = (p[t] - c) + s * (double)e[t];
 }

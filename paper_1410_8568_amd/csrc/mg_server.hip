@@ -71,6 +71,7 @@ struct mg_server {
 namespace {
 
 void complete(mg_server* sv, Job* j, int status) {
+    solve_release(j->S);
     std::lock_guard<std::mutex> lk(sv->mu);
     j->result.status = status;
     j->result.finish_ms = sv->now_ms();
@@ -94,6 +95,7 @@ bool start_job(mg_server* sv, Job* j) {
     h->g = j->req.grid;
     h->o = sv->o.solver;
     h->o.profile = 0;
+    h->o.graph = 1;
     plan(&h->g, &h->o, &h->L);
     h->ws = sv->arena + j->off;
     h->stream = sv->streams[j->slot];

@@ -40,7 +40,8 @@ class Grid(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
                 ("n_coarsest", ctypes.c_int), ("inner_m", ctypes.c_int),
-                ("max_cycles", ctypes.c_int), ("profile", ctypes.c_int), ("tile", ctypes.c_int)]
+                ("max_cycles", ctypes.c_int), ("profile", ctypes.c_int), ("tile", ctypes.c_int),
+                ("graph", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -128,13 +129,14 @@ class MGError(RuntimeError):
 
 
 def options(precision="fp64", nu1=2, nu2=2, n_coarsest=4, inner_m=2, max_cycles=100, profile=False,
-            tile=0):
+            tile=0, graph=False):
     o = Options()
     lib().mg_default_options(ctypes.byref(o))
     o.precision = {"fp64": MG_FP64, "fp32_refined": MG_FP32_REFINED}[precision]
     o.nu1, o.nu2, o.n_coarsest, o.inner_m, o.max_cycles = nu1, nu2, n_coarsest, inner_m, max_cycles
     o.profile = 1 if profile else 0
     o.tile = tile
+    o.graph = 1 if graph else 0
     return o
 
 

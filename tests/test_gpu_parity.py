@@ -175,3 +175,38 @@ def test_fused_sweep_tiles_bit_identical(precision, n):
         p, st = gpu_solve(P, precision=precision, tol=1e-10, tile=tile)
         assert st["history"] == ref_st["history"], tile
         assert np.array_equal(p, ref_p), tile
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+@pytest.mark.parametrize("n", [(64, 64, 64), (96, 48, 32)])
+def test_graph_replay_bit_identical(precision, n):
+    """One captured iteration replayed for every iteration (with the host's
+    convergence test and copies in between) gives exactly the eager results."""
+    P = ragged_problem(n, seed=9)
+    ref_p, ref_st = gpu_solve(P, precision=precision, tol=1e-10, graph=False)
+    p, st = gpu_solve(P, precision=precision, tol=1e-10, graph=True)
+    assert st["cycles"] == ref_st["cycles"] and st["cycles"] > 3
+    assert st["history"] == ref_st["history"]
+    assert np.array_equal(p, ref_p)
+
+
+def test_config2_full_size_matches_oracle():
+    """512^3 Fourier-perturbed drop splash in the benchmark's configuration
+    (coarsest 8^3, default options): both GPU solvers against the oracle's FP64
+    solve, and their residual recomputed with the oracle's operator."""
+    P = inputs.config2(512)
+    ref = oracle.solve(P.bx, P.by, P.bz, P.b, tol=1e-10, n_coarsest=8)
+    assert ref["status"] == "converged"
+    bbar = P.b - P.b.mean()
+    nb = np.linalg.norm(bbar)
+    for precision in ("fp64", "fp32_refined"):
+        p, st = gpu_solve(P, precision=precision, tol=1e-10, n_coarsest=8)
+        assert st["rc"] == 0, st
+        r = oracle.residual(P.bx, P.by, P.bz, p, bbar)
+        assert np.linalg.norm(r) / nb <= 1e-10
+        assert abs(p.mean()) <= 1e-12 * np.abs(p).max()
+        err = rel(p, ref["p"])
+        print(f"512^3 {precision}: cycles {st['cycles']} rel residual {st['rel_residual']:.3e} "
+              f"oracle rel err {err:.3e}", flush=True)
+        assert err <= 1e-8
+        del p
