@@ -66,6 +66,18 @@ __device__ __forceinline__ T stencil_diag(T w0, T w1, T w2, T w3, T w4, T w5) {
     return ((((w0 + w1) + w2) + w3) + w4) + w5;
 }
 
+// Gauss-Seidel quotient (s - b) / d.  FP32: the hardware reciprocal (within
+// 1 ulp) and one Newton correction of the quotient from its exact fma residual,
+// which is within about half an ulp (and almost always equal to the correctly
+// rounded quotient) at a fraction of the cost of the full IEEE division
+// sequence.  FP64 divides exactly.
+__device__ __forceinline__ float gs_quot(float num, float d) {
+    const float r = __builtin_amdgcn_rcpf(d);
+    const float q = num * r;
+    return fmaf(fmaf(-d, q, num), r, q);
+}
+__device__ __forceinline__ double gs_quot(double num, double d) { return num / d; }
+
 // Neighbour sum s = sum_f beta_f p_nb and diagonal d = sum_f beta_f for cell
 // (i,j,k); out-of-grid neighbours read as 0 (their face coefficient is 0).
 template <class T>
@@ -394,7 +406,7 @@ __global__ void __launch_bounds__(BX* BY) k_rb_half(Lvl<T> L, T* __restrict__ p,
         T s, d;
         nbsum(L, p, i, j, k, s, d);
         size_t c = cidx(i, j, k, L.nx, L.ny);
-        p[c] = (s - b[c]) / d;
+        p[c] = gs_quot(s - b[c], d);
     }
 }
 
@@ -439,6 +451,53 @@ __device__ __forceinline__ int xcd_tile(int w, int nwg) {
     return x * q + min(x, r) + m;
 }
 
+// Raw buffer access: a resource (base address, range, format word) in scalar
+// registers plus a per-lane 32-bit byte offset, so a load costs no per-lane
+// address arithmetic and no 64-bit address registers.  The format word is the
+// gfx9-family one for untyped 32-bit elements; the range is the maximum (every
+// access here is in bounds by construction).
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+__device__ float buf_ld_f32(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.f32");
+__device__ f32x2 buf_ld_f32x2(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.v2f32");
+__device__ double buf_ld_f64(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.f64");
+__device__ f64x2 buf_ld_f64x2(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.v2f64");
+__device__ void buf_st_f32x2(f32x2 v, i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.store.v2f32");
+__device__ void buf_st_f64x2(f64x2 v, i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.store.v2f64");
+
+__device__ __forceinline__ i32x4 buf_rsrc(const void* p) {
+    const uint64_t a = (uint64_t)p;
+    i32x4 r;
+    r.x = __builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+    r.y = __builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));   // stride 0
+    r.z = -1;
+    r.w = 0x00020000;
+    return r;
+}
+__device__ __forceinline__ float2 buf_ld2(i32x4 r, uint32_t off, const float*) {
+    const f32x2 v = buf_ld_f32x2(r, (int)off, 0, 0);
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 buf_ld2(i32x4 r, uint32_t off, const double*) {
+    const f64x2 v = buf_ld_f64x2(r, (int)off, 0, 0);
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float buf_ld1(i32x4 r, uint32_t off, const float*) { return buf_ld_f32(r, (int)off, 0, 0); }
+__device__ __forceinline__ double buf_ld1(i32x4 r, uint32_t off, const double*) { return buf_ld_f64(r, (int)off, 0, 0); }
+__device__ __forceinline__ void buf_st2(float2 v, i32x4 r, uint32_t off) {
+    f32x2 w;
+    w.x = v.x;
+    w.y = v.y;
+    buf_st_f32x2(w, r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_st2(double2 v, i32x4 r, uint32_t off) {
+    f64x2 w;
+    w.x = v.x;
+    w.y = v.y;
+    buf_st_f64x2(w, r, (int)off, 0, 0);
+}
+
 // Compile-time loop: f(std::integral_constant<int, i>) for i = B .. E-1, so that
 // arrays indexed by i are only ever indexed by constants (and stay in registers).
 template <int B, int E, class F>
@@ -464,21 +523,24 @@ struct Vec2<double> {
 // in a single pass over HBM, out of place (pin -> pout, so tiles never race).
 //
 // A workgroup owns a TX x TY column of cells and marches upward through a chunk
-// of kc planes.  The sweeps are 2*NSW colour stages; stage h (h = 1 .. R,
-// R = 2*NSW) updates colour c0 (h odd) or 1 - c0 (h even) on plane t - h + 1
-// at step t, on the tile plus a ring of R - h cells.  Planes of pin are staged
-// in LDS with an R-cell ring and updated in place stage by stage; a ring value
-// is the same one the neighbouring tile computes, bit for bit, so after stage R
-// the tile's plane t - R + 1 is final and written out.  Planes below k0 and
-// above k1 - 1 are recomputed redundantly, so chunks are independent.
+// of kc planes.  The sweeps are R = 2*NSW colour stages; stage h (h = 1 .. R)
+// updates colour c0 (h odd) or 1 - c0 (h even) on plane t - h + 1 at step t, on
+// the tile plus a ring of R - h cells.  Planes of pin are staged in LDS with an
+// R-cell ring and updated in place stage by stage; a ring value is the same one
+// the neighbouring tile computes, bit for bit, so after stage R the tile's plane
+// t - R + 1 is final and written out.  Planes below k0 and above k1 - 1 are
+// recomputed redundantly, so chunks are independent.
 //
 // Thread (q, lj) owns the aligned cell pair i = i0-R+2q, i0-R+1+2q of row
 // j = j0-R+1+lj, so every global access is a 2-element vector; at step t all
 // R stages fall on the same cell of the pair (the colour of a column flips
-// from plane to plane).  The face coefficients and right-hand side of the pair
-// are kept in registers for the R planes in flight.  The global loads of plane
-// t+2 (pin) and t+1 (faces, b) are issued before the compute of step t.
-// Requires even nx (every smoothed level has one).
+// from plane to plane).  In LDS the even and odd columns of a row are kept in
+// two half rows, so the lanes of a wave, each touching one cell of its pair,
+// hit consecutive banks.  The face coefficients and right-hand side of the pair
+// stay in registers while their plane is in flight (the upper z-face of a cell
+// is the lower z-face of the plane above).  Planes of pin and the z-faces are
+// loaded two steps ahead, the other faces and b one step ahead, before the
+// compute of the current step.  Requires even nx (every smoothed level has one).
 //
 // With shift_sum non-null, every value of pin is first reduced by
 // shift_sum[0] / n_cells (the mean-zero projection of the previous iterate, done
@@ -489,12 +551,13 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
                int tiles_x, int tiles_y, const double* __restrict__ shift_sum, double n_cells) {
     using V = typename Vec2<T>::type;
     constexpr int R = 2 * NSW;                  // LDS ring = number of colour stages
-    constexpr int W = TX + 2 * R, H = TY + 2 * R;
+    constexpr int W = TX + 2 * R, H = TY + 2 * R, W2 = W / 2;
     constexpr int PW = TX / 2 + R, PH = TY + 2 * (R - 1), NT = PW * PH;
     constexpr int NS = R + 3;                   // plane slots: R + 2 live, one being refilled
-    constexpr int NV = H * (W / 2);             // pairs in a staged plane
+    constexpr int PL = H * W;                   // elements of a staged plane
+    constexpr int NV = H * W2;                  // pairs in a staged plane
     constexpr int NP = (NV + NT - 1) / NT;      // staged pairs per thread
-    __shared__ __align__(16) T sp[NS][H][W];
+    __shared__ __align__(16) T sp[NS * PL];
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, chunk = tile / (tiles_x * tiles_y);
@@ -507,131 +570,230 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
     const bool inpair = ia >= 0 && ia < nx && gj >= 0 && gj < ny;   // nx even: both cells in or both out
     const size_t plane = (size_t)nx * ny;
     const T shift = shift_sum ? (T)(shift_sum[0] / n_cells) : T(0);
+    const int tfirst = k0 - R + 1, tlast = k1 + R - 2;
 
+    // LDS position of (row r, column c) within a plane: (2r + (c & 1)) * W2 + c / 2.
     // Global loads are unconditional (clamped to a valid address) so the compiler
     // can leave them in flight until first use; out-of-grid values are zeroed
-    // where they are written to LDS or consumed.
-    long roff[NP];    // offset of staged pair u within a plane, clamped
-    int rpos[NP];     // its LDS position (-1: no pair u for this thread)
-    bool rin[NP];     // inside the grid
+    // where they are written to LDS or consumed.  Addresses are a per-plane base
+    // (uniform) plus a fixed 32-bit byte offset per thread.
+    uint32_t roff[NP];   // byte offset of staged pair u within a plane, clamped
+    int rpos[NP];        // LDS position of its even cell (-1: no pair u for this thread)
+    bool rin[NP];        // inside the grid
 #pragma unroll
     for (int u = 0; u < NP; u++) {
         const int v = tid + u * NT;
-        const int vi = v % (W / 2), vj = v / (W / 2);
+        const int vi = v % W2, vj = v / W2;
         const int ii = i0 - R + 2 * vi, jj = j0 - R + vj;
-        rpos[u] = v < NV ? vj * W + 2 * vi : -1;
+        rpos[u] = v < NV ? vj * W + vi : -1;
         rin[u] = v < NV && ii >= 0 && ii < nx && jj >= 0 && jj < ny;
-        roff[u] = rin[u] ? (long)jj * nx + ii : 0;
+        roff[u] = rin[u] ? (uint32_t)(jj * nx + ii) * (uint32_t)sizeof(T) : 0u;
     }
-    T* const spf = &sp[0][0][0];
-    auto slot = [](int k) { return (k + 4 * NS) % NS; };
+    constexpr const T* tag = nullptr;
     auto kclamp = [&](int k) { return k < 0 ? 0 : (k >= nz ? nz - 1 : k); };
     auto fetch_ring = [&](int k, V* v) {
-        const size_t base = (size_t)kclamp(k) * plane;
+        const i32x4 r = buf_rsrc(pin + (size_t)kclamp(k) * plane);
 #pragma unroll
-        for (int u = 0; u < NP; u++) v[u] = *reinterpret_cast<const V*>(pin + base + roff[u]);
+        for (int u = 0; u < NP; u++) v[u] = buf_ld2(r, roff[u], tag);
     };
-    auto store_ring = [&](int k, const V* v) {
-        T* dst = spf + slot(k) * (H * W);
+    auto store_ring = [&](int sl, int k, const V* v) {
+        T* dst = sp + sl * PL;
         const bool kin = k >= 0 && k < nz;
 #pragma unroll
         for (int u = 0; u < NP; u++)
             if (rpos[u] >= 0) {
-                V x;
                 const bool ok = kin && rin[u];
-                x.x = ok ? v[u].x - shift : T(0);
-                x.y = ok ? v[u].y - shift : T(0);
-                *reinterpret_cast<V*>(dst + rpos[u]) = x;
+                dst[rpos[u]] = ok ? v[u].x - shift : T(0);
+                dst[rpos[u] + W2] = ok ? v[u].y - shift : T(0);
             }
     };
-    // face coefficients and right-hand side of the pair on one plane; the upper
-    // faces past the last cell (wall) are masked where they are used
+    // x- and y-face coefficients and right-hand side of the pair on one plane (the
+    // z-faces are kept apart: a plane's lower z-faces are also the upper z-faces
+    // of the plane below and are loaded one step earlier)
     struct FB {
-        V fx, fy, fyu, fz, fzu, bb;
+        V fx, fy, fyu, bb;
         T fxu;   // upper x-face of the second cell
     };
     const bool xu = ia + 2 < nx, yu = gj + 1 < ny;
-    const size_t col = inpair ? (size_t)gj * nx + ia : 0;
-    // Offsets of the upper faces (0 at a wall, where the value is masked).  They
-    // pass through an empty asm so the compiler cannot see that they may equal
-    // another load's address and fold the loads into a copy (a copy would have
-    // to wait for the load right away).
-    int xo = xu ? 2 : 0, yo = yu ? nx : 0;
-    asm volatile("" : "+v"(xo), "+v"(yo));
-    auto fetch_fb = [&](int k) {
-        FB f;
-        const int kk = kclamp(k);
-        const size_t c = (size_t)kk * plane + col;
-        const size_t zo = kk + 1 < nz ? plane : 0;   // uniform: no copy of another load
-        f.fx = *reinterpret_cast<const V*>(L.fx + c);
-        f.fxu = L.fx[c + xo];
-        f.fy = *reinterpret_cast<const V*>(L.fy + c);
-        f.fyu = *reinterpret_cast<const V*>(L.fy + c + yo);
-        f.fz = *reinterpret_cast<const V*>(L.fz + c);
-        f.fzu = *reinterpret_cast<const V*>(L.fz + c + zo);
-        f.bb = *reinterpret_cast<const V*>(b + c);
-        return f;
+    const uint32_t cb = inpair ? (uint32_t)(gj * nx + ia) * (uint32_t)sizeof(T) : 0u;
+    // Offsets of the upper faces (those of the pair itself at a wall, where the
+    // value is masked).  They pass through an empty asm so the compiler cannot
+    // see that they may equal another load's address and fold the loads into a
+    // copy (a copy would have to wait for the load right away).
+    uint32_t cbx = cb + (xu ? 2u : 0u) * (uint32_t)sizeof(T), cby = cb + (yu ? (uint32_t)nx * sizeof(T) : 0u);
+    asm volatile("" : "+v"(cbx), "+v"(cby));
+    auto fetch_fb = [&](int k, FB& f) {
+        const size_t pk = (size_t)kclamp(k) * plane;
+        const i32x4 rx = buf_rsrc(L.fx + pk), ry = buf_rsrc(L.fy + pk);
+        f.fx = buf_ld2(rx, cb, tag);
+        f.fxu = buf_ld1(rx, cbx, tag);
+        f.fy = buf_ld2(ry, cb, tag);
+        f.fyu = buf_ld2(ry, cby, tag);
+        f.bb = buf_ld2(buf_rsrc(b + pk), cb, tag);
     };
-    // Gauss-Seidel value of cell e (0: first of the pair) on plane k with faces f.
-    auto gs = [&](const FB& f, int e, int k) {
-        const int col = 2 * q + e;
-        const T w0 = e ? f.fx.y : f.fx.x;
-        const T w1 = e ? (xu ? f.fxu : T(0)) : f.fx.y;
-        const T w2 = e ? f.fy.y : f.fy.x;
-        const T w3 = yu ? (e ? f.fyu.y : f.fyu.x) : T(0);
-        const T w4 = e ? f.fz.y : f.fz.x;
-        const T w5 = k + 1 < nz ? (e ? f.fzu.y : f.fzu.x) : T(0);
-        const T bb = e ? f.bb.y : f.bb.x;
-        T(*c)[W] = sp[slot(k)];
-        const T s = stencil_sum(w0, w1, w2, w3, w4, w5, c[row][col - 1], c[row][col + 1], c[row - 1][col],
-                                c[row + 1][col], sp[slot(k - 1)][row][col], sp[slot(k + 1)][row][col]);
-        return (s - bb) / stencil_diag(w0, w1, w2, w3, w4, w5);
+    auto fetch_fz = [&](int k) { return buf_ld2(buf_rsrc(L.fz + (size_t)kclamp(k) * plane), cb, tag); };
+    // Zero the faces that lie on an upper wall (once per plane, one step after
+    // its loads were issued).
+    auto mask_fb = [&](FB& f) {
+        if (!xu) f.fxu = T(0);
+        if (!yu) f.fyu.x = f.fyu.y = T(0);
     };
+    auto mask_fz = [&](int k, V& f) {
+        if (k >= nz) f.x = f.y = T(0);
+    };
+    // Ring distance of each cell of the pair: stage h updates the cell when it is
+    // within R - h of the tile (large when the pair is outside the grid).
+    auto ring_dist = [&](int c) {
+        const int dx = max(R - c, c - (R + TX - 1)), dy = max(R - row, row - (R + TY - 1));
+        return inpair ? max(max(dx, dy), 0) : 4 * R;
+    };
+    const int dist0 = ring_dist(2 * q), dist1 = ring_dist(2 * q + 1);
 
     V ring[NP];
-    const int tfirst = k0 - R + 1, tlast = k1 + R - 2;
-    fetch_ring(tfirst - 1, ring);
-    store_ring(tfirst - 1, ring);
-    fetch_ring(tfirst, ring);
-    store_ring(tfirst, ring);
-    fetch_ring(tfirst + 1, ring);
-    FB fq[R];                 // fq[h-1]: faces of plane t-h+1 during step t
-    FB fnext = fetch_fb(tfirst);
-    static_for<0, R>([&](auto hc) { fq[decltype(hc)::value] = fnext; });
-    for (int t = tfirst; t <= tlast; t++) {
-        store_ring(t + 1, ring);
-        static_for<1, R>([&](auto hc) {
-            constexpr int h = R - decltype(hc)::value;   // R-1 down to 1
-            fq[h] = fq[h - 1];
-        });
-        fq[0] = fnext;
-        lds_barrier();
-        fetch_ring(t + 2, ring);     // in flight during this step
-        fnext = fetch_fb(t + 1);
-        // the cell of the pair that stage 1 updates on plane t; every stage of
-        // this step updates the same cell (on its own plane)
-        const int e = (c0 + i0 + gj + t) & 1;
-        const int col = 2 * q + e;
-        static_for<1, R + 1>([&](auto hc) {
-            constexpr int h = decltype(hc)::value;
-            const int z = t - h + 1;       // this stage's plane
-            constexpr int rg = R - h;      // this stage's ring width
-            const bool in_ring = col >= R - rg && col < R + TX + rg && row >= R - rg && row < R + TY + rg;
-            const bool in_z = z >= 0 && z < nz && z >= k0 - rg && z < k1 + rg;
-            if constexpr (h < R) {
-                if (inpair && in_ring && in_z) sp[slot(z)][row][col] = gs(fq[h - 1], e, z);
+    if constexpr (sizeof(T) == 4 || NSW == 1) {
+        // One step per iteration; the register queues shift by one plane per
+        // step (fewer live registers, so more waves fit per CU).
+        FB fq[R + 1];     // fq[h]: x/y faces and b of plane t - h + 1 during step t (fq[0] in flight)
+        V fzq[R + 2];     // fzq[h]: z-faces of plane t - h + 2 during step t (fzq[0] in flight)
+        auto lslot = [&](int k) { return (k - tfirst + NS) % NS; };
+        fetch_ring(tfirst - 1, ring);
+        store_ring(lslot(tfirst - 1), tfirst - 1, ring);
+        fetch_ring(tfirst, ring);
+        store_ring(lslot(tfirst), tfirst, ring);
+        fetch_ring(tfirst + 1, ring);
+        fetch_fb(tfirst, fq[0]);
+        fzq[0] = fetch_fz(tfirst + 1);
+        fzq[1] = fetch_fz(tfirst);
+        static_for<1, R + 1>([&](auto sc) { fq[decltype(sc)::value] = fq[0]; });
+        static_for<2, R + 2>([&](auto sc) { fzq[decltype(sc)::value] = fzq[1]; });
+        for (int t = tfirst; t <= tlast; t++) {
+            static_for<0, R>([&](auto hc) {
+                constexpr int h = R - decltype(hc)::value;
+                fq[h] = fq[h - 1];
+            });
+            static_for<0, R + 1>([&](auto hc) {
+                constexpr int h = R + 1 - decltype(hc)::value;
+                fzq[h] = fzq[h - 1];
+            });
+            store_ring(lslot(t + 1), t + 1, ring);
+            mask_fb(fq[1]);
+            mask_fz(t + 1, fzq[1]);
+            lds_barrier();
+            fetch_ring(t + 2, ring);                  // in flight during this step
+            fetch_fb(t + 1, fq[0]);
+            fzq[0] = fetch_fz(t + 2);
+            const int e = (c0 + i0 + gj + t) & 1;
+            const int dist = e ? dist1 : dist0;
+            const int oc = (2 * row + e) * W2 + q;                    // the cell
+            const int ol = e ? 2 * row * W2 + q : (2 * row + 1) * W2 + q - 1;
+            const int orr = e ? 2 * row * W2 + q + 1 : (2 * row + 1) * W2 + q;
+            const int opart = (2 * row + (e ^ 1)) * W2 + q;           // its pair partner
+            static_for<1, R + 1>([&](auto hc) {
+                constexpr int h = decltype(hc)::value;
+                constexpr int rg = R - h;                               // this stage's ring width
+                const int z = t - h + 1;
+                const int sz = lslot(z), sd = lslot(z - 1), su = lslot(z + 1);
+                const bool in_z = z >= 0 && z < nz && z >= k0 - rg && z < k1 + rg;
+                const FB& f = fq[h];
+                const T w0 = e ? f.fx.y : f.fx.x;
+                const T w1 = e ? f.fxu : f.fx.y;
+                const T w2 = e ? f.fy.y : f.fy.x;
+                const T w3 = e ? f.fyu.y : f.fyu.x;
+                const T w4 = e ? fzq[h + 1].y : fzq[h + 1].x;
+                const T w5 = e ? fzq[h].y : fzq[h].x;
+                const T bb = e ? f.bb.y : f.bb.x;
+                const T* c = sp + sz * PL;
+                const T s = stencil_sum(w0, w1, w2, w3, w4, w5, c[ol], c[orr], c[oc - W], c[oc + W],
+                                        sp[sd * PL + oc], sp[su * PL + oc]);
+                const T vnew = gs_quot(s - bb, stencil_diag(w0, w1, w2, w3, w4, w5));
+                if constexpr (h < R) {
+                    if (in_z && dist <= rg) sp[sz * PL + oc] = vnew;
+                    lds_barrier();
+                } else if (in_z && dist <= rg) {
+                    // the tile's plane z is final: this cell from stage R, its pair
+                    // partner from stage R-1 of the previous step
+                    const T vold = c[opart];
+                    V out;
+                    out.x = e ? vold : vnew;
+                    out.y = e ? vnew : vold;
+                    buf_st2(out, buf_rsrc(pout + (size_t)z * plane), cb);
+                }
+            });
+        }
+    } else {
+        // FP64, several sweeps: the loop is unrolled by NS steps, so every queue
+        // slot and LDS slot is a compile-time index (no register shifts,
+        // immediate LDS offsets); measured faster here despite more registers.
+        // Plane z is held in LDS slot, face slot and z-face slot (z - tfirst) mod NS.
+        // Loads in flight at step t: pin of plane t+2, x/y faces and b of plane t+1,
+        // z-faces of plane t+2.
+        FB fq[NS];
+        V fzq[NS];
+        fetch_ring(tfirst - 1, ring);
+        store_ring(NS - 1, tfirst - 1, ring);
+        fetch_ring(tfirst, ring);
+        store_ring(0, tfirst, ring);
+        fetch_ring(tfirst + 1, ring);
+        fetch_fb(tfirst, fq[0]);
+        fzq[0] = fetch_fz(tfirst);
+        fzq[1] = fetch_fz(tfirst + 1);
+        static_for<1, NS>([&](auto sc) { fq[decltype(sc)::value] = fq[0]; });
+        static_for<2, NS>([&](auto sc) { fzq[decltype(sc)::value] = fzq[0]; });
+        for (int tg = tfirst; tg <= tlast; tg += NS) {
+            static_for<0, NS>([&](auto uc) {
+                constexpr int u = decltype(uc)::value;
+                constexpr int s0 = u % NS, s1 = (u + 1) % NS, s2 = (u + 2) % NS;
+                const int t = tg + u;
+                if (t > tlast) return;
+                store_ring(s1, t + 1, ring);
+                mask_fb(fq[s0]);
+                mask_fz(t + 1, fzq[s1]);
                 lds_barrier();
-            } else if (inpair && in_ring && in_z) {
-                // the tile's plane z is final: this cell from stage R, its pair
-                // partner from stage R-1 of the previous step
-                const T vnew = gs(fq[h - 1], e, z);
-                const T vold = sp[slot(z)][row][2 * q + (e ^ 1)];
-                V out;
-                out.x = e ? vold : vnew;
-                out.y = e ? vnew : vold;
-                *reinterpret_cast<V*>(pout + (size_t)z * plane + (size_t)gj * nx + ia) = out;
-            }
-        });
+                fetch_ring(t + 2, ring);                  // in flight during this step
+                fetch_fb(t + 1, fq[s1]);
+                fzq[s2] = fetch_fz(t + 2);
+                // the cell of the pair that stage 1 updates on plane t; every stage of
+                // this step updates the same cell (on its own plane)
+                const int e = (c0 + i0 + gj + t) & 1;
+                const int dist = e ? dist1 : dist0;
+                const int oc = (2 * row + e) * W2 + q;                    // the cell
+                const int ol = e ? 2 * row * W2 + q : (2 * row + 1) * W2 + q - 1;
+                const int orr = e ? 2 * row * W2 + q + 1 : (2 * row + 1) * W2 + q;
+                const int opart = (2 * row + (e ^ 1)) * W2 + q;           // its pair partner
+                static_for<1, R + 1>([&](auto hc) {
+                    constexpr int h = decltype(hc)::value;
+                    constexpr int sz = (u - h + 1 + 2 * NS) % NS;         // slot of this stage's plane
+                    constexpr int sd = (sz + NS - 1) % NS, su = (sz + 1) % NS;
+                    constexpr int rg = R - h;                               // this stage's ring width
+                    const int z = t - h + 1;
+                    const bool in_z = z >= 0 && z < nz && z >= k0 - rg && z < k1 + rg;
+                    const FB& f = fq[sz];
+                    const T w0 = e ? f.fx.y : f.fx.x;
+                    const T w1 = e ? f.fxu : f.fx.y;
+                    const T w2 = e ? f.fy.y : f.fy.x;
+                    const T w3 = e ? f.fyu.y : f.fyu.x;
+                    const T w4 = e ? fzq[sz].y : fzq[sz].x;
+                    const T w5 = e ? fzq[su].y : fzq[su].x;
+                    const T bb = e ? f.bb.y : f.bb.x;
+                    const T* c = sp + sz * PL;
+                    const T s = stencil_sum(w0, w1, w2, w3, w4, w5, c[ol], c[orr], c[oc - W], c[oc + W],
+                                            sp[sd * PL + oc], sp[su * PL + oc]);
+                    const T vnew = gs_quot(s - bb, stencil_diag(w0, w1, w2, w3, w4, w5));
+                    if constexpr (h < R) {
+                        if (in_z && dist <= rg) sp[sz * PL + oc] = vnew;
+                        lds_barrier();
+                    } else if (in_z && dist <= rg) {
+                        // the tile's plane z is final: this cell from stage R, its pair
+                        // partner from stage R-1 of the previous step
+                        const T vold = c[opart];
+                        V out;
+                        out.x = e ? vold : vnew;
+                        out.y = e ? vnew : vold;
+                        buf_st2(out, buf_rsrc(pout + (size_t)z * plane), cb);
+                    }
+                });
+            });
+        }
     }
 }
 
