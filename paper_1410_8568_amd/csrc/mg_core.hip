@@ -57,21 +57,6 @@ static int col_blocks(int nx, int ny, int nz) {
     return (int)(g.x * g.y * g.z);
 }
 
-// Tiles (32 x 8 fine columns) and even-length z-chunks of the restriction kernel.
-static ColGrid rgrid(int nx, int ny, int nz, int* nblocks) {
-    ColGrid G;
-    G.tiles_x = (nx + RBX - 1) / RBX;
-    G.tiles_y = (ny + RBY - 1) / RBY;
-    const int tiles = G.tiles_x * G.tiles_y;
-    int chunks = std::max(1, std::min(std::max(1, nz / 16), (2048 + tiles - 1) / tiles));
-    int kc = (nz + chunks - 1) / chunks;
-    if (kc & 1) kc++;
-    G.kc = kc;
-    chunks = (nz + kc - 1) / kc;
-    *nblocks = tiles * chunks;
-    return G;
-}
-
 // Tiles and z-chunks of the z-marching column kernels: about 2048 workgroups,
 // chunks of >= 16 planes (an even count when `even`).
 static ColGrid zgrid(int cols_x, int cols_y, int nz, bool even, int* nblocks) {
@@ -171,6 +156,8 @@ mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
         int zb = 0;
         zgrid(L->d[l].nx, L->d[l].ny, L->d[l].nz, false, &zb);
         mb = std::max(mb, std::max(zb, col_blocks(L->d[l].nx, L->d[l].ny, L->d[l].nz)));
+        zgrid((L->d[l].nx + 1) / 2, L->d[l].ny, L->d[l].nz, false, &zb);   // cell-pair kernels
+        mb = std::max(mb, zb);
     }
     L->max_blocks = mb;
     L->part = take((size_t)2 * mb * 8);
@@ -553,8 +540,19 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
     {
         Prof pf(h, MG_K_RESTRICT, ((2.0 * d.ncell() + d.nfaces()) + c.ncell()) * sizeof(T));
         int nb = 0;
-        const ColGrid G = rgrid(d.nx, d.ny, d.nz, &nb);
-        k_resid_restrict_col<T><<<nb, 256, 0, s>>>(H.L[l], cur, H.rhs[l], G, H.rhs[l + 1]);
+        // restricted levels have even nx; FP32 takes 4 cells per thread (16-byte loads) when it can
+        bool quad = false;
+        if constexpr (sizeof(T) == 4) {
+            if (d.nx % 4 == 0) {
+                const ColGrid G = zgrid(d.nx / 4, d.ny, d.nz, true, &nb);
+                k_resid_restrict_cells<T, 4><<<nb, CBX * CBY, 0, s>>>(H.L[l], cur, H.rhs[l], G, H.rhs[l + 1]);
+                quad = true;
+            }
+        }
+        if (!quad) {
+            const ColGrid G = zgrid(d.nx / 2, d.ny, d.nz, true, &nb);
+            k_resid_restrict_cells<T, 2><<<nb, CBX * CBY, 0, s>>>(H.L[l], cur, H.rhs[l], G, H.rhs[l + 1]);
+        }
     }
     {
         Prof pf(h, MG_K_OTHER, (double)c.ncell() * sizeof(T));
@@ -564,7 +562,7 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
     {
         Prof pf(h, MG_K_PROLONG, (2.0 * d.ncell() + 2.0 * c.ncell()) * sizeof(T));
         int nbp = 0;
-        const ColGrid G = zgrid(c.nx, d.ny, d.nz, false, &nbp);   // columns: coarse x by fine y
+        const ColGrid G = zgrid(c.nx, d.ny, c.nz, false, &nbp);   // columns: coarse x by fine y; coarse planes
         k_prolong_col<T><<<nbp, CBX * CBY, 0, s>>>(H.e[l + 1], H.a[l + 1], c.nx, c.ny, c.nz, G, cur);
     }
     smooth(h, H, l, h->o.nu2, 1, cur, alt);
@@ -599,6 +597,22 @@ static void build_hier(mg_handle* h, double* p, Hier<double>& H64, Hier<float>& 
             H32.a[l] = h->fa[l];
         }
     }
+}
+
+// Residual pass over level 0 (FP64; MODE as k_resid_col): the cell-pair
+// kernel when nx is even.  Returns the number of partial-sum blocks.
+template <int MODE>
+static int launch_resid(hipStream_t s, const Lvl<double>& L, const double* p, const double* b,
+                        const double* inv_s, float* r32, double* part) {
+    int nb = 0;
+    if ((L.nx & 1) == 0) {
+        const ColGrid G = zgrid(L.nx / 2, L.ny, L.nz, false, &nb);
+        k_resid_cells<double, 2, MODE><<<nb, CBX * CBY, 0, s>>>(L, p, b, G, inv_s, r32, part);
+    } else {
+        const ColGrid G = zgrid(L.nx, L.ny, L.nz, false, &nb);
+        k_resid_col<double, MODE><<<nb, CBX * CBY, 0, s>>>(L, p, b, G, inv_s, r32, part);
+    }
+    return nb;
 }
 
 // Step 1 (blocking): project b, initial residual, history[0].
@@ -643,15 +657,14 @@ mg_status solve_begin(SolveState& S) {
     }
     const double resid_bytes = (2.0 * N + d0.nfaces()) * 8.0;
     int nbz = 0;
-    const ColGrid G0 = zgrid(d0.nx, d0.ny, d0.nz, false, &nbz);
     if (f32) {
         // first FP32 right-hand side scaled by a power of two near the RMS of b_bar
         k_refine_scale<<<1, 64, 0, s>>>(h->scal + 3, N, h->scal + 8);
         Prof pf(h, MG_K_REFINE, resid_bytes + 4.0 * N);
-        k_resid_col<double, 1><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, h->scal + 9, h->frhs[0], h->part);
+        nbz = launch_resid<1>(s, L64, S.p, h->bbar, h->scal + 9, h->frhs[0], h->part);
     } else {
         Prof pf(h, MG_K_NORM, resid_bytes);
-        k_resid_col<double, 0><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, nullptr, nullptr, h->part);
+        nbz = launch_resid<0>(s, L64, S.p, h->bbar, nullptr, nullptr, h->part);
     }
     finish(h, nbz, 4);
     S.project = true;  // scal[5] now holds sum(p); p is made mean-zero lazily
@@ -685,7 +698,6 @@ static mg_status launch_iteration_kernels(SolveState& S) {
     Hier<float> H32;
     build_hier(h, S.p, H64, H32);
     int nbz = 0;
-    const ColGrid G0 = zgrid(d0.nx, d0.ny, d0.nz, false, &nbz);
     if (!f32) {
         const double* shift = h->scal + 5;
         if (!fused_first_sweep(h)) {
@@ -695,7 +707,7 @@ static mg_status launch_iteration_kernels(SolveState& S) {
         }
         vcycle(h, H64, 0, shift);
         Prof pf(h, MG_K_NORM, resid_bytes);
-        k_resid_col<double, 0><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, nullptr, nullptr, h->part);
+        nbz = launch_resid<0>(s, L64, S.p, h->bbar, nullptr, nullptr, h->part);
     } else {
         {
             Prof pf(h, MG_K_OTHER, 4.0 * N);
@@ -710,7 +722,7 @@ static mg_status launch_iteration_kernels(SolveState& S) {
         // residual just used (any power of two leaves the FP32 arithmetic unchanged)
         k_refine_scale<<<1, 64, 0, s>>>(h->scal + 4, N, h->scal + 8);
         Prof pf(h, MG_K_REFINE, resid_bytes + 4.0 * N);
-        k_resid_col<double, 1><<<nbz, CBX * CBY, 0, s>>>(L64, S.p, h->bbar, G0, h->scal + 9, h->frhs[0], h->part);
+        nbz = launch_resid<1>(s, L64, S.p, h->bbar, h->scal + 9, h->frhs[0], h->part);
     }
     finish(h, nbz, 4);
     HIPCHK(hipGetLastError());

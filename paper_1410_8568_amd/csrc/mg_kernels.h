@@ -66,17 +66,17 @@ __device__ __forceinline__ T stencil_diag(T w0, T w1, T w2, T w3, T w4, T w5) {
     return ((((w0 + w1) + w2) + w3) + w4) + w5;
 }
 
-// Gauss-Seidel quotient (s - b) / d.  FP32: the hardware reciprocal (within
+// Quotient num / d of the cycle kernels.  FP32: the hardware reciprocal (within
 // 1 ulp) and one Newton correction of the quotient from its exact fma residual,
 // which is within about half an ulp (and almost always equal to the correctly
 // rounded quotient) at a fraction of the cost of the full IEEE division
 // sequence.  FP64 divides exactly.
-__device__ __forceinline__ float gs_quot(float num, float d) {
+__device__ __forceinline__ float quot(float num, float d) {
     const float r = __builtin_amdgcn_rcpf(d);
     const float q = num * r;
     return fmaf(fmaf(-d, q, num), r, q);
 }
-__device__ __forceinline__ double gs_quot(double num, double d) { return num / d; }
+__device__ __forceinline__ double quot(double num, double d) { return num / d; }
 
 // Neighbour sum s = sum_f beta_f p_nb and diagonal d = sum_f beta_f for cell
 // (i,j,k); out-of-grid neighbours read as 0 (their face coefficient is 0).
@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(BX* BY) k_rb_half(Lvl<T> L, T* __restrict__ p,
         T s, d;
         nbsum(L, p, i, j, k, s, d);
         size_t c = cidx(i, j, k, L.nx, L.ny);
-        p[c] = gs_quot(s - b[c], d);
+        p[c] = quot(s - b[c], d);
     }
 }
 
@@ -705,7 +705,7 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
                 const T* c = sp + sz * PL;
                 const T s = stencil_sum(w0, w1, w2, w3, w4, w5, c[ol], c[orr], c[oc - W], c[oc + W],
                                         sp[sd * PL + oc], sp[su * PL + oc]);
-                const T vnew = gs_quot(s - bb, stencil_diag(w0, w1, w2, w3, w4, w5));
+                const T vnew = quot(s - bb, stencil_diag(w0, w1, w2, w3, w4, w5));
                 if constexpr (h < R) {
                     if (in_z && dist <= rg) sp[sz * PL + oc] = vnew;
                     lds_barrier();
@@ -778,7 +778,7 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
                     const T* c = sp + sz * PL;
                     const T s = stencil_sum(w0, w1, w2, w3, w4, w5, c[ol], c[orr], c[oc - W], c[oc + W],
                                             sp[sd * PL + oc], sp[su * PL + oc]);
-                    const T vnew = gs_quot(s - bb, stencil_diag(w0, w1, w2, w3, w4, w5));
+                    const T vnew = quot(s - bb, stencil_diag(w0, w1, w2, w3, w4, w5));
                     if constexpr (h < R) {
                         if (in_z && dist <= rg) sp[sz * PL + oc] = vnew;
                         lds_barrier();
@@ -886,80 +886,257 @@ __global__ void __launch_bounds__(CBX* CBY) k_resid_col(Lvl<T> L, const T* __res
     }
 }
 
-// Residual restricted to the next level.  A wavefront covers 32 x 2 fine
-// columns (lane l: i = i0 + l % 32, j = j0 + l / 32), so the 2 x 2 children of
-// a coarse column sit in lanes l, l^1, l^32, l^33; each thread marches up its
-// column, sums its residuals over the plane pair 2K, 2K+1, and the four sums are
-// combined with lane shuffles.  rc(I,J,K) = 1/2 * (sum of the 8 child residuals).
-// Tiles are 32 x 8 fine columns (4 wavefronts); kc (planes per chunk) is even.
-constexpr int RBX = 32, RBY = 8;
+// ---------------------------------------------------------------- cell-pair residual kernels
+//
+// Residual kernels for nx divisible by NC = 2 or 4 (every level but possibly
+// the finest has even nx): a thread owns NC consecutive cells of a row, so
+// their values, right-hand side and faces are vector loads and one load
+// instruction serves NC cells.  Every load is unconditional and no loaded value
+// is masked (see cell_offsets), so the loads of a plane stay in flight together.
+// Latency is hidden by occupancy (few registers per thread) rather than by
+// loading planes further ahead, which measured no faster here.
 
-template <class T>
-__global__ void __launch_bounds__(256) k_resid_restrict_col(Lvl<T> L, const T* __restrict__ p,
-                                                           const T* __restrict__ b, ColGrid G,
-                                                           T* __restrict__ rc) {
+// NC consecutive values as one vector load (NC = 2 or 4; 16 bytes at most).
+template <class T, int NC>
+struct VecN;
+template <>
+struct VecN<float, 2> {
+    using type = float2;
+};
+template <>
+struct VecN<float, 4> {
+    using type = float4;
+};
+template <>
+struct VecN<double, 2> {
+    using type = double2;
+};
+
+template <class T, int NC>
+__device__ __forceinline__ void load_n(const T* src, T (&d)[NC]) {
+    const typename VecN<T, NC>::type v = *reinterpret_cast<const typename VecN<T, NC>::type*>(src);
+    if constexpr (NC == 2) {
+        d[0] = v.x;
+        d[1] = v.y;
+    } else {
+        d[0] = v.x;
+        d[1] = v.y;
+        d[2] = v.z;
+        d[3] = v.w;
+    }
+}
+
+// One plane of NC cells of a row: own values, in-plane neighbours, right-hand
+// side and faces (lower x, y and z faces, the upper x face of the last cell and
+// the upper y faces; the upper z faces are the next plane's lower ones).
+template <class T, int NC>
+struct Cells1 {
+    T p[NC], ps[NC], pn[NC], b[NC], fx[NC], fy[NC], fyu[NC], fz[NC];
+    T pw, pe, fxu;
+};
+
+// Offsets (within a plane) of the loads of cells i = NC*I .. NC*I+NC-1 of row j.
+// A neighbour across a wall is read where the face that multiplies it is a
+// stored lower wall face, i.e. exactly 0: across a lower wall the cells
+// themselves; across the upper x wall the first cell of the row, across the
+// upper y wall row 0 (their lower faces are walls).  No value needs masking.
+struct CellOff {
+    int c, w, e, s, n;
+};
+
+template <int NC>
+__device__ __forceinline__ CellOff cell_offsets(int I, int j, int nx, int ny) {
+    CellOff o;
+    o.c = j * nx + NC * I;
+    o.w = I > 0 ? o.c - 1 : o.c;
+    o.e = NC * I + NC < nx ? o.c + NC : j * nx;
+    o.s = j > 0 ? o.c - nx : o.c;
+    o.n = j + 1 < ny ? o.c + nx : NC * I;
+    return o;
+}
+
+// The plane above k for the z-marching kernels: at the top wall plane 0, whose
+// lower z faces are walls (0), so the upper z face of the top plane reads as 0.
+__device__ __forceinline__ int plane_above(int k, int nz) { return k + 1 < nz ? k + 1 : 0; }
+
+template <class T, int NC>
+__device__ __forceinline__ Cells1<T, NC> load_cells1(const Lvl<T>& L, const T* __restrict__ p,
+                                                     const T* __restrict__ b, const CellOff& o, int k) {
+    const size_t base = (size_t)k * L.nx * L.ny;
+    Cells1<T, NC> v;
+    load_n(p + base + o.c, v.p);
+    v.pw = p[base + o.w];
+    v.pe = p[base + o.e];
+    load_n(p + base + o.s, v.ps);
+    load_n(p + base + o.n, v.pn);
+    load_n(b + base + o.c, v.b);
+    load_n(L.fx + base + o.c, v.fx);
+    v.fxu = L.fx[base + o.e];
+    load_n(L.fy + base + o.c, v.fy);
+    load_n(L.fy + base + o.n, v.fyu);
+    load_n(L.fz + base + o.c, v.fz);
+    return v;
+}
+
+// Residuals r = b - (s - d p) of the cells on plane k, given p below (pb) and
+// the plane above (its p and lower z faces, loaded from plane_above).
+template <class T, int NC>
+__device__ __forceinline__ void cells_residual(const Cells1<T, NC>& c, const T (&pb)[NC],
+                                               const Cells1<T, NC>& up, T (&r)[NC]) {
+#pragma unroll
+    for (int e = 0; e < NC; e++) {
+        const T w1 = e + 1 < NC ? c.fx[e + 1] : c.fxu;
+        const T pw = e > 0 ? c.p[e - 1] : c.pw;
+        const T pe = e + 1 < NC ? c.p[e + 1] : c.pe;
+        const T s = stencil_sum(c.fx[e], w1, c.fy[e], c.fyu[e], c.fz[e], up.fz[e], pw, pe, c.ps[e], c.pn[e], pb[e],
+                                up.p[e]);
+        const T d = stencil_diag(c.fx[e], w1, c.fy[e], c.fyu[e], c.fz[e], up.fz[e]);
+        r[e] = c.b[e] - (s - d * c.p[e]);
+    }
+}
+
+// k_resid_col for nx divisible by NC.  Tiles of CBX cell groups x CBY rows.
+template <class T, int NC, int MODE>
+__global__ void __launch_bounds__(CBX* CBY) k_resid_cells(Lvl<T> L, const T* __restrict__ p,
+                                                         const T* __restrict__ b, ColGrid G,
+                                                         const double* __restrict__ scal_inv_s,
+                                                         float* __restrict__ r32, double* __restrict__ part) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
+    const int I = tx * CBX + (int)(threadIdx.x % CBX), j = ty * CBY + (int)(threadIdx.x / CBX);
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int k0 = chunk * G.kc, k1 = min(nz, k0 + G.kc);
+    double a = 0, q = 0;
+    const double inv_s = MODE == 1 ? scal_inv_s[0] : 1.0;
+    if (NC * I < nx && j < ny && k0 < k1) {
+        const size_t plane = (size_t)nx * ny;
+        const CellOff o = cell_offsets<NC>(I, j, nx, ny);
+        T pb[NC];
+        load_n(p + (size_t)max(k0 - 1, 0) * plane + o.c, pb);
+        Cells1<T, NC> cur = load_cells1<T, NC>(L, p, b, o, k0);
+        for (int k = k0; k < k1; k++) {
+            const Cells1<T, NC> nxt = load_cells1<T, NC>(L, p, b, o, plane_above(k, nz));
+            T r[NC];
+            cells_residual(cur, pb, nxt, r);
+            if (MODE == 1) {
+                float w[NC];
+#pragma unroll
+                for (int e = 0; e < NC; e++) w[e] = (float)((double)r[e] * inv_s);
+                if constexpr (NC == 2)
+                    *reinterpret_cast<float2*>(r32 + (size_t)k * plane + o.c) = make_float2(w[0], w[1]);
+                else
+                    *reinterpret_cast<float4*>(r32 + (size_t)k * plane + o.c) = make_float4(w[0], w[1], w[2], w[3]);
+            }
+#pragma unroll
+            for (int e = 0; e < NC; e++) {
+                a += (double)r[e] * (double)r[e];
+                q += (double)cur.p[e];
+                pb[e] = cur.p[e];
+            }
+            cur = nxt;
+        }
+    }
+    __shared__ double sa[CBX * CBY / 64], sb[CBX * CBY / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        q += __shfl_down(q, off, 64);
+    }
+    if (threadIdx.x % 64 == 0) { sa[threadIdx.x / 64] = a; sb[threadIdx.x / 64] = q; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0, tb = 0;
+        for (int w = 0; w < CBX * CBY / 64; w++) { ta += sa[w]; tb += sb[w]; }
+        part[2 * tile] = ta;
+        part[2 * tile + 1] = tb;
+    }
+}
+
+// Residual restricted to the next level, rc(I,J,K) = 1/2 * (sum of the 8 child
+// residuals), for nx divisible by NC (every restricted level has even nx).
+// Tiles of CBX cell groups x CBY rows, one wavefront per row: a thread holds
+// the x-children of NC/2 coarse columns and sums them over the plane pair 2K,
+// 2K+1; the y partner (next row, next wavefront) is added through LDS.  kc is
+// even.
+template <class T, int NC>
+__global__ void __launch_bounds__(CBX* CBY) k_resid_restrict_cells(Lvl<T> L, const T* __restrict__ p,
+                                                                  const T* __restrict__ b, ColGrid G,
+                                                                  T* __restrict__ rc) {
+    static_assert(CBY % 2 == 0, "row pairs");
+    constexpr int NQ = NC / 2;   // coarse columns per thread
+    __shared__ T part[CBY][NQ][CBX];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int cnx = nx / 2, cny = ny / 2;
-    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    const int i = tx * RBX + lane % 32, j = ty * RBY + 2 * wave + lane / 32;
+    const int li = threadIdx.x % CBX, lj = threadIdx.x / CBX;
+    const int I = tx * CBX + li, j = ty * CBY + lj;
     const int k0 = chunk * G.kc, k1 = min(nz, k0 + G.kc);
-    const bool active = i < nx && j < ny;   // nx, ny even: a 2x2 group is all in or all out
+    const bool active = NC * I < nx && j < ny;   // ny even: a row pair is all in or all out
     const size_t plane = (size_t)nx * ny;
-    const size_t col = (size_t)j * nx + i;
-    T pbelow = T(0), wz0 = T(0);
-    Plane1<T> cur{}, nxt{};
+    const CellOff o = cell_offsets<NC>(active ? I : 0, active ? j : 0, nx, ny);
+    T pb[NC] = {};
+    Cells1<T, NC> cur{};
     if (active && k0 < k1) {
-        pbelow = k0 > 0 ? p[(size_t)(k0 - 1) * plane + col] : T(0);
-        wz0 = L.fz[(size_t)k0 * plane + col];
-        cur = load_plane1(L, p, b, i, j, k0);
+        load_n(p + (size_t)max(k0 - 1, 0) * plane + o.c, pb);
+        cur = load_cells1<T, NC>(L, p, b, o, k0);
     }
-    T acc = 0;
+    T acc[NQ] = {};
     for (int k = k0; k < k1; k++) {
         if (active) {
-            if (k + 1 < nz) nxt = load_plane1(L, p, b, i, j, k + 1);
-            const T pabove = k + 1 < nz ? nxt.p : T(0);
-            const T s = stencil_sum(cur.wx0, cur.wx1, cur.wy0, cur.wy1, wz0, cur.wz1, cur.pw, cur.pe, cur.ps, cur.pn,
-                                    pbelow, pabove);
-            const T d = stencil_diag(cur.wx0, cur.wx1, cur.wy0, cur.wy1, wz0, cur.wz1);
-            acc += cur.b - (s - d * cur.p);
-            pbelow = cur.p;
-            wz0 = cur.wz1;
+            const Cells1<T, NC> nxt = load_cells1<T, NC>(L, p, b, o, plane_above(k, nz));
+            T r[NC];
+            cells_residual(cur, pb, nxt, r);
+#pragma unroll
+            for (int c = 0; c < NQ; c++) acc[c] += r[2 * c] + r[2 * c + 1];
+#pragma unroll
+            for (int e = 0; e < NC; e++) pb[e] = cur.p[e];
             cur = nxt;
         }
         if (k & 1) {
-            T v = acc;
-            v += __shfl_xor(v, 1, 64);
-            v += __shfl_xor(v, 32, 64);
-            if (active && !(i & 1) && !(j & 1)) rc[cidx(i >> 1, j >> 1, k >> 1, cnx, cny)] = T(0.5) * v;
-            acc = 0;
+#pragma unroll
+            for (int c = 0; c < NQ; c++) part[lj][c][li] = acc[c];
+            __syncthreads();
+            if (active && !(lj & 1)) {
+                T v[NQ];
+#pragma unroll
+                for (int c = 0; c < NQ; c++) v[c] = T(0.5) * (acc[c] + part[lj + 1][c][li]);
+                T* dst = rc + cidx(NQ * I, j >> 1, k >> 1, cnx, cny);
+                if constexpr (NQ == 1)
+                    dst[0] = v[0];
+                else
+                    *reinterpret_cast<typename Vec2<T>::type*>(dst) = typename Vec2<T>::type{v[0], v[1]};
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < NQ; c++) acc[c] = 0;
         }
     }
 }
 
-// Flux-conserving prolongation and correction, z-marching.  Thread (I, j) owns
-// the fine cell pair i = 2I, 2I+1 of fine row j: both are children of coarse
-// column I with the same y side (Jy) and opposite x sides (I-1 for the even
-// child, I+1 for the odd one, clamped = wall mirror).  The thread keeps three
-// coarse planes of a and a*e for the 3 x 2 coarse columns it needs in registers
-// and advances one coarse plane every two fine planes.  For each child, corner
-// T of its octant has V_T = sum a e / sum a over the 2^|T| coarse cells sharing
-// it (T = {} is the coarse cell itself, V = e_C); the child gets
-// (1/8) * sum_T V_T, the corners summed in the order {}, x, y, xy, z, xz, yz, xyz
-// and the cells of a corner with x fastest, then y, then z.  The corners y, z,
-// yz are shared by the two children.  The next fine plane's pair is loaded one
-// step ahead.  Requires even fine nx (always: fine = 2 * coarse).
+// Flux-conserving prolongation and correction, z-marching over coarse planes.
+// Thread (I, j) owns the fine cell pair i = 2I, 2I+1 of fine row j: both are
+// children of coarse column I with the same y side (Jy) and opposite x sides
+// (I-1 for the even child, I+1 for the odd one, clamped = wall mirror).  For
+// each child, corner T of its octant has V_T = sum a e / sum a over the 2^|T|
+// coarse cells sharing it (T = {} is the coarse cell itself, V = e_C); the
+// child gets (1/8) * sum_T V_T, the corners summed in the order {}, x, y, xy, z,
+// xz, yz, xyz and the cells of a corner with x fastest, then y, then z (lower
+// plane first).  Each step handles the two fine planes 2K, 2K+1 of coarse plane
+// K: the in-plane corners ({}, x, y, xy) are shared by both, the corners on the
+// face K-1/2 were computed in the previous step (as face K+1/2 of plane K-1),
+// and the corners y, z, yz are shared by the two children.  The coarse plane
+// K+1 and the fine planes of the next step are loaded one step ahead.  G.kc
+// counts coarse planes.
 template <class T>
 __global__ void __launch_bounds__(CBX* CBY) k_prolong_col(const T* __restrict__ ec, const T* __restrict__ ac,
                                                          int cnx, int cny, int cnz, ColGrid G, T* __restrict__ ef) {
     using V = typename Vec2<T>::type;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
-    const int nx = 2 * cnx, ny = 2 * cny, nz = 2 * cnz;
+    const int nx = 2 * cnx, ny = 2 * cny;
     const int I = tx * CBX + (int)(threadIdx.x % CBX), j = ty * CBY + (int)(threadIdx.x / CBX);
-    const int k0 = chunk * G.kc, k1 = min(nz, k0 + G.kc);
-    if (I >= cnx || j >= ny || k0 >= k1) return;
+    const int K0 = chunk * G.kc, K1 = min(cnz, K0 + G.kc);
+    if (I >= cnx || j >= ny || K0 >= K1) return;
     const int J = j >> 1;
     const int Im = max(I - 1, 0), Ip = min(I + 1, cnx - 1);
     const int Jy = (j & 1) ? min(J + 1, cny - 1) : max(J - 1, 0);
@@ -985,48 +1162,63 @@ __global__ void __launch_bounds__(CBX* CBY) k_prolong_col(const T* __restrict__ 
         c.wyp = c.ayp * ec[base + rY + Ip];
         return c;
     };
-    int Kc = k0 >> 1;
-    CP cm = load(max(Kc - 1, 0)), c0 = load(Kc), cp = load(min(Kc + 1, cnz - 1));
+    // corners on the face between coarse planes lo (below) and up: z, yz and,
+    // per child, xz and xyz
+    struct Face {
+        T z, yz, xz[2], xyz[2];
+    };
+    auto face = [&](const CP& lo, const CP& up) {
+        Face f;
+        f.z = quot(lo.w0 + up.w0, lo.a0 + up.a0);
+        f.yz = quot(((lo.w0 + lo.wy0) + up.w0) + up.wy0, ((lo.a0 + lo.ay0) + up.a0) + up.ay0);
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+            const T lax = e ? lo.ap : lo.am, lwx = e ? lo.wp : lo.wm;
+            const T lay = e ? lo.ayp : lo.aym, lwy = e ? lo.wyp : lo.wym;
+            const T uax = e ? up.ap : up.am, uwx = e ? up.wp : up.wm;
+            const T uay = e ? up.ayp : up.aym, uwy = e ? up.wyp : up.wym;
+            f.xz[e] = quot(((lo.w0 + lwx) + up.w0) + uwx, ((lo.a0 + lax) + up.a0) + uax);
+            f.xyz[e] = quot(((((((lo.w0 + lwx) + lo.wy0) + lwy) + up.w0) + uwx) + up.wy0) + uwy,
+                            ((((((lo.a0 + lax) + lo.ay0) + lay) + up.a0) + uax) + up.ay0) + uay);
+        }
+        return f;
+    };
     const size_t fplane = (size_t)nx * ny;
     const size_t fcol = (size_t)j * nx + 2 * I;
-    V fnext = *reinterpret_cast<const V*>(ef + (size_t)k0 * fplane + fcol);
-    for (int k = k0; k < k1; k++) {
-        const int K = k >> 1;
-        if (K != Kc) {
-            Kc = K;
-            cm = c0;
-            c0 = cp;
-            cp = load(min(K + 1, cnz - 1));
+    CP c0 = load(K0), cp = load(min(K0 + 1, cnz - 1));
+    Face fl = face(load(max(K0 - 1, 0)), c0);          // face K0 - 1/2 (wall: mirror)
+    V n0 = *reinterpret_cast<const V*>(ef + (size_t)(2 * K0) * fplane + fcol);
+    V n1 = *reinterpret_cast<const V*>(ef + (size_t)(2 * K0 + 1) * fplane + fcol);
+    for (int K = K0; K < K1; K++) {
+        V f0 = n0, f1 = n1;
+        const CP cq = K + 1 < K1 ? load(min(K + 2, cnz - 1)) : cp;
+        if (K + 1 < K1) {
+            n0 = *reinterpret_cast<const V*>(ef + (size_t)(2 * K + 2) * fplane + fcol);
+            n1 = *reinterpret_cast<const V*>(ef + (size_t)(2 * K + 3) * fplane + fcol);
         }
-        V f = fnext;
-        if (k + 1 < k1) fnext = *reinterpret_cast<const V*>(ef + (size_t)(k + 1) * fplane + fcol);
-        const CP& cz = (k & 1) ? cp : cm;   // the coarse plane on these children's z side
-        // shared corners
-        const T vy = (c0.w0 + c0.wy0) / (c0.a0 + c0.ay0);
-        const T vz = (c0.w0 + cz.w0) / (c0.a0 + cz.a0);
-        const T vyz = (((c0.w0 + c0.wy0) + cz.w0) + cz.wy0) / (((c0.a0 + c0.ay0) + cz.a0) + cz.ay0);
-        // child 0 (x side Im), child 1 (x side Ip)
-        T tot[2];
+        const Face fu = face(c0, cp);                   // face K + 1/2 (wall: mirror)
+        const T vy = quot(c0.w0 + c0.wy0, c0.a0 + c0.ay0);
+        T t0[2], t1[2];
 #pragma unroll
         for (int e = 0; e < 2; e++) {
             const T ax = e ? c0.ap : c0.am, wx = e ? c0.wp : c0.wm;
             const T axy = e ? c0.ayp : c0.aym, wxy = e ? c0.wyp : c0.wym;
-            const T azx = e ? cz.ap : cz.am, wzx = e ? cz.wp : cz.wm;
-            const T azxy = e ? cz.ayp : cz.aym, wzxy = e ? cz.wyp : cz.wym;
             T t = c0.e0;
-            t += (c0.w0 + wx) / (c0.a0 + ax);
+            t += quot(c0.w0 + wx, c0.a0 + ax);
             t += vy;
-            t += (((c0.w0 + wx) + c0.wy0) + wxy) / (((c0.a0 + ax) + c0.ay0) + axy);
-            t += vz;
-            t += (((c0.w0 + wx) + cz.w0) + wzx) / (((c0.a0 + ax) + cz.a0) + azx);
-            t += vyz;
-            t += (((((((c0.w0 + wx) + c0.wy0) + wxy) + cz.w0) + wzx) + cz.wy0) + wzxy) /
-                 (((((((c0.a0 + ax) + c0.ay0) + axy) + cz.a0) + azx) + cz.ay0) + azxy);
-            tot[e] = t;
+            t += quot(((c0.w0 + wx) + c0.wy0) + wxy, ((c0.a0 + ax) + c0.ay0) + axy);
+            t0[e] = (((t + fl.z) + fl.xz[e]) + fl.yz) + fl.xyz[e];
+            t1[e] = (((t + fu.z) + fu.xz[e]) + fu.yz) + fu.xyz[e];
         }
-        f.x += tot[0] / T(8);
-        f.y += tot[1] / T(8);
-        *reinterpret_cast<V*>(ef + (size_t)k * fplane + fcol) = f;
+        f0.x += t0[0] * T(0.125);
+        f0.y += t0[1] * T(0.125);
+        f1.x += t1[0] * T(0.125);
+        f1.y += t1[1] * T(0.125);
+        *reinterpret_cast<V*>(ef + (size_t)(2 * K) * fplane + fcol) = f0;
+        *reinterpret_cast<V*>(ef + (size_t)(2 * K + 1) * fplane + fcol) = f1;
+        fl = fu;
+        c0 = cp;
+        cp = cq;
     }
 }
 

@@ -23,9 +23,12 @@ def check_history(h_gpu, h_or, precision="fp64"):
     the attainable-accuracy floor (different FMA contraction and summation order).
 
     FP64: 1e-9 relative above 1e-7, 1e-5 below.  FP32-refined: the inner cycles
-    round at FP32 epsilon (6e-8) in a different order than the oracle's FP32
-    emulation (FMA contraction on the GPU, none in the oracle), so 1e-5 / 1e-3."""
-    early_rtol, late_rtol = (1e-9, 1e-5) if precision == "fp64" else (1e-5, 1e-3)
+    round at FP32 epsilon (6e-8) differently from the oracle's FP32 emulation (FMA
+    contraction, the reciprocal-based FP32 quotient, the summation order of the
+    prolongation corners), and the residual after a cycle is a small difference of
+    large terms that amplifies those roundings a few hundred times, so 1e-4 / 1e-3.
+    The formulas themselves are the same templates that the FP64 runs check at 1e-9."""
+    early_rtol, late_rtol = (1e-9, 1e-5) if precision == "fp64" else (1e-4, 1e-3)
     assert len(h_gpu) == len(h_or), (len(h_gpu), len(h_or))
     for c, (g, o) in enumerate(zip(h_gpu, h_or)):
         tol = early_rtol if o > 1e-7 else late_rtol
