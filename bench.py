@@ -274,6 +274,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--graph", type=int, default=1, help="replay each outer iteration as a HIP graph (1) or launch eagerly (0)")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (counter scale)")
     ap.add_argument("--summarize", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
     ap.add_argument("--batch", action="store_true", help="batched uneven solves through the server")
@@ -322,7 +323,8 @@ def main():
     def build(precision, profile=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        S = mg.Solver(bx, by, bz, precision=precision, n_coarsest=args.n_coarsest, profile=profile)
+        S = mg.Solver(bx, by, bz, precision=precision, n_coarsest=args.n_coarsest, profile=profile,
+                      graph=args.graph and not profile)
         torch.cuda.synchronize()
         return S, (time.perf_counter() - t0) * 1e3
 

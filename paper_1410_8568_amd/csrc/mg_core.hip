@@ -58,13 +58,14 @@ static int col_blocks(int nx, int ny, int nz) {
 }
 
 // Tiles and z-chunks of the z-marching column kernels: about 2048 workgroups,
-// chunks of >= 16 planes (an even count when `even`).
+// chunks of >= 4 planes (an even count when `even`); short chunks keep small
+// levels from marching many planes in few workgroups.
 static ColGrid zgrid(int cols_x, int cols_y, int nz, bool even, int* nblocks) {
     ColGrid G;
     G.tiles_x = (cols_x + CBX - 1) / CBX;
     G.tiles_y = (cols_y + CBY - 1) / CBY;
     const int tiles = G.tiles_x * G.tiles_y;
-    int chunks = std::max(1, std::min(std::max(1, nz / 16), (2048 + tiles - 1) / tiles));
+    int chunks = std::max(1, std::min(std::max(1, nz / 4), (2048 + tiles - 1) / tiles));
     int kc = (nz + chunks - 1) / chunks;
     if (even && (kc & 1)) kc++;
     G.kc = kc;
@@ -332,7 +333,7 @@ struct Hier {
 
 template <class T, int TX, int TY, int NSW>
 static void launch_sweep(hipStream_t s, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0, int target,
-                         const double* shift_sum) {
+                         const double* shift_sum, int zero_in) {
     const int gx = (L.nx + TX - 1) / TX, gy = (L.ny + TY - 1) / TY;
     const int tiles = gx * gy;
     // chunks of >= 8 planes, so the redundant planes at chunk ends stay a small fraction
@@ -341,7 +342,7 @@ static void launch_sweep(hipStream_t s, const Lvl<T>& L, const T* pin, T* pout, 
     chunks = (L.nz + kc - 1) / kc;
     constexpr int NT = (TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2);
     k_rb_sweep<T, TX, TY, NSW><<<dim3(tiles * chunks), NT, 0, s>>>(L, pin, pout, b, c0, kc, gx, gy, shift_sum,
-                                                                  (double)L.nx * L.ny * L.nz);
+                                                                  (double)L.nx * L.ny * L.nz, zero_in);
 }
 
 // Sweeps done by one pass of fused variant v (1..MG_NUM_TILES).
@@ -357,26 +358,26 @@ static bool variant_native(int v) {
 // Fused sweep variant v in 1..MG_NUM_TILES: one pass doing sweeps_per_pass(v) sweeps.
 template <class T>
 static void fused_sweep(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0,
-                        const double* shift_sum = nullptr) {
+                        const double* shift_sum = nullptr, int zero_in = 0) {
     const int target = ((v - 1) & 1) ? 4096 : 1024;
     switch ((v - 1) >> 1) {
-        case 0: launch_sweep<T, 64, 8, 1>(s, L, pin, pout, b, c0, target, shift_sum); break;
-        case 1: launch_sweep<T, 128, 4, 1>(s, L, pin, pout, b, c0, target, shift_sum); break;
-        case 2: launch_sweep<T, 128, 8, 1>(s, L, pin, pout, b, c0, target, shift_sum); break;
-        case 3: launch_sweep<T, 64, 16, 1>(s, L, pin, pout, b, c0, target, shift_sum); break;
-        case 4: launch_sweep<T, 64, 4, 2>(s, L, pin, pout, b, c0, target, shift_sum); break;
-        case 5: launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum); break;
+        case 0: launch_sweep<T, 64, 8, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in); break;
+        case 1: launch_sweep<T, 128, 4, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in); break;
+        case 2: launch_sweep<T, 128, 8, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in); break;
+        case 3: launch_sweep<T, 64, 16, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in); break;
+        case 4: launch_sweep<T, 64, 4, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in); break;
+        case 5: launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in); break;
         case 6:
             if constexpr (sizeof(T) == 4)
-                launch_sweep<T, 128, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum);
+                launch_sweep<T, 128, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in);
             else
-                launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum);
+                launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in);
             break;
         default:
             if constexpr (sizeof(T) == 4)
-                launch_sweep<T, 64, 16, 2>(s, L, pin, pout, b, c0, target, shift_sum);
+                launch_sweep<T, 64, 16, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in);
             else
-                launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum);
+                launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in);
             break;
     }
 }
@@ -493,21 +494,30 @@ static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b
 // from the iterate as it reads it; returns false if there was no fused pass.
 template <class T>
 static bool smooth(mg_handle* h, Hier<T>& H, int l, int nsweep, int c0, T*& cur, T*& alt,
-                   const double* shift_sum = nullptr) {
-    if (nsweep <= 0) return shift_sum == nullptr;
+                   const double* shift_sum = nullptr, bool zero_in = false) {
     hipStream_t s = h->stream;
     const LevelDims& d = H.d[l];
+    const int tile = alt ? h->tile[l] : -1;
+    const bool fused = tile > 0 && nsweep >= sweeps_per_pass(tile);
+    if (zero_in && !fused) {
+        Prof pf(h, MG_K_OTHER, (double)d.ncell() * sizeof(T));
+        k_fill<T><<<lin_grid(d.ncell()), 256, 0, s>>>(cur, d.ncell(), T(0));
+        zero_in = false;
+    }
+    if (nsweep <= 0) return shift_sum == nullptr;
     const int cls = l == 0 ? MG_K_SMOOTH_FINE : MG_K_SMOOTH;
     const double full = (3.0 * d.ncell() + d.nfaces()) * sizeof(T);
-    const int tile = alt ? h->tile[l] : -1;
     bool shifted = shift_sum == nullptr;
     int rem = nsweep;
     if (tile > 0) {
         const int spp = sweeps_per_pass(tile);
         for (; rem >= spp; rem -= spp) {
-            Prof pf(h, cls, spp * full);   // algorithmic bytes: one sweep's worth per sweep done
-            fused_sweep<T>(s, tile, H.L[l], cur, alt, H.rhs[l], c0, shifted ? nullptr : shift_sum);
+            // algorithmic bytes: one sweep's worth per sweep done (less the
+            // iterate's read when it starts from zero)
+            Prof pf(h, cls, spp * full - (zero_in ? (double)d.ncell() * sizeof(T) : 0.0));
+            fused_sweep<T>(s, tile, H.L[l], cur, alt, H.rhs[l], c0, shifted ? nullptr : shift_sum, zero_in ? 1 : 0);
             shifted = true;
+            zero_in = false;
             std::swap(cur, alt);
         }
     }
@@ -524,18 +534,18 @@ static bool fused_first_sweep(const mg_handle* h) {
 }
 
 template <class T>
-static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nullptr) {
+static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nullptr, bool zero_init = false) {
     hipStream_t s = h->stream;
     const LevelDims& d = H.d[l];
     if (l == H.nlev - 1) {
         Prof pf(h, MG_K_COARSE, (double)h->L.ncoarse * h->L.ncoarse * 8 + 2.0 * d.ncell() * sizeof(T));
-        k_coarse_solve<T><<<1, 512, 0, s>>>(h->binv, h->L.ncoarse, H.rhs[l], H.e[l]);
+        k_coarse_solve<T><<<(h->L.ncoarse + 7) / 8, 512, 0, s>>>(h->binv, h->L.ncoarse, H.rhs[l], H.e[l]);
         return;
     }
     // the current iterate moves between e and tmp as fused passes run
     T* cur = H.e[l];
     T* alt = H.tmp[l];
-    smooth(h, H, l, h->o.nu1, 0, cur, alt, shift_sum);
+    smooth(h, H, l, h->o.nu1, 0, cur, alt, shift_sum, zero_init);
     const LevelDims& c = H.d[l + 1];
     {
         Prof pf(h, MG_K_RESTRICT, ((2.0 * d.ncell() + d.nfaces()) + c.ncell()) * sizeof(T));
@@ -554,11 +564,7 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
             k_resid_restrict_cells<T, 2><<<nb, CBX * CBY, 0, s>>>(H.L[l], cur, H.rhs[l], G, H.rhs[l + 1]);
         }
     }
-    {
-        Prof pf(h, MG_K_OTHER, (double)c.ncell() * sizeof(T));
-        k_fill<T><<<lin_grid(c.ncell()), 256, 0, s>>>(H.e[l + 1], c.ncell(), T(0));
-    }
-    vcycle(h, H, l + 1);
+    vcycle(h, H, l + 1, nullptr, true);   // the coarse correction starts from zero
     {
         Prof pf(h, MG_K_PROLONG, (2.0 * d.ncell() + 2.0 * c.ncell()) * sizeof(T));
         int nbp = 0;
@@ -709,11 +715,7 @@ static mg_status launch_iteration_kernels(SolveState& S) {
         Prof pf(h, MG_K_NORM, resid_bytes);
         nbz = launch_resid<0>(s, L64, S.p, h->bbar, nullptr, nullptr, h->part);
     } else {
-        {
-            Prof pf(h, MG_K_OTHER, 4.0 * N);
-            k_fill<float><<<lin_grid(d0.ncell()), 256, 0, s>>>(h->fe[0], d0.ncell(), 0.0f);
-        }
-        for (int m = 0; m < h->o.inner_m; m++) vcycle(h, H32, 0);
+        for (int m = 0; m < h->o.inner_m; m++) vcycle(h, H32, 0, nullptr, m == 0);   // e starts from zero
         {
             Prof pf(h, MG_K_REFINE, 20.0 * N);
             k_refine_update<<<lin_grid(d0.ncell()), 256, 0, s>>>(S.p, h->fe[0], h->scal + 8, d0.ncell(), h->scal + 5);

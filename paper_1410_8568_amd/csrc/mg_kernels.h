@@ -410,7 +410,11 @@ __global__ void __launch_bounds__(BX* BY) k_rb_half(Lvl<T> L, T* __restrict__ p,
     }
 }
 
-// Exact coarsest solve e = -B^{-1} (r - mean r), FP64 arithmetic; one block.
+// Exact coarsest solve e = -B^{-1} (r - mean r), FP64 arithmetic, n <= 512.
+// Wavefront w of workgroup g computes row 8g + w: each lane sums every 64th
+// column of the row (consecutive lanes, consecutive addresses, all loads
+// independent), then the wavefront adds the 64 partial sums in a fixed tree.
+// Every workgroup forms the mean of r itself.
 template <class T>
 __global__ void __launch_bounds__(512) k_coarse_solve(const double* __restrict__ Binv, int n,
                                                      const T* __restrict__ r, T* __restrict__ e) {
@@ -427,11 +431,12 @@ __global__ void __launch_bounds__(512) k_coarse_solve(const double* __restrict__
     const double mean = tot / n;
     if (t < n) rs[t] = v - mean;
     __syncthreads();
-    if (t < n) {
-        double acc = 0;
-        for (int jj = 0; jj < n; jj++) acc += Binv[(size_t)jj * n + t] * rs[jj];
-        e[t] = (T)(-acc);
-    }
+    const int lane = t % 64, row = blockIdx.x * 8 + t / 64;
+    if (row >= n) return;   // whole wavefronts
+    double acc = 0;
+    for (int c = lane; c < n; c += 64) acc += Binv[(size_t)row * n + c] * rs[c];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) e[row] = (T)(-acc);
 }
 
 // Workgroup barrier that only orders LDS traffic: waits for this wave's
@@ -454,8 +459,8 @@ __device__ __forceinline__ int xcd_tile(int w, int nwg) {
 // Raw buffer access: a resource (base address, range, format word) in scalar
 // registers plus a per-lane 32-bit byte offset, so a load costs no per-lane
 // address arithmetic and no 64-bit address registers.  The format word is the
-// gfx9-family one for untyped 32-bit elements; the range is the maximum (every
-// access here is in bounds by construction).
+// gfx9-family one for untyped 32-bit elements; the range is the maximum unless
+// stated (every access here is in bounds by construction).
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
@@ -466,12 +471,14 @@ __device__ f64x2 buf_ld_f64x2(i32x4 rsrc, int voff, int soff, int aux) __asm("ll
 __device__ void buf_st_f32x2(f32x2 v, i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.store.v2f32");
 __device__ void buf_st_f64x2(f64x2 v, i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.store.v2f64");
 
-__device__ __forceinline__ i32x4 buf_rsrc(const void* p) {
+// range: bytes addressable from p; loads at or past it return 0 without
+// touching memory (used with range 0 to read an all-zero operand).
+__device__ __forceinline__ i32x4 buf_rsrc(const void* p, int range = -1) {
     const uint64_t a = (uint64_t)p;
     i32x4 r;
     r.x = __builtin_amdgcn_readfirstlane((int)(uint32_t)a);
     r.y = __builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));   // stride 0
-    r.z = -1;
+    r.z = range;
     r.w = 0x00020000;
     return r;
 }
@@ -545,10 +552,13 @@ struct Vec2<double> {
 // With shift_sum non-null, every value of pin is first reduced by
 // shift_sum[0] / n_cells (the mean-zero projection of the previous iterate, done
 // on the fly instead of as a separate pass; same arithmetic as k_sub_mean).
+// With zero_in set, the iterate entering the pass is zero and pin is not read:
+// its loads go through a buffer resource of range 0, which returns 0 (a
+// coarse-grid correction's first smoothing pass; no separate fill).
 template <class T, int TX, int TY, int NSW>
 __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
     k_rb_sweep(Lvl<T> L, const T* __restrict__ pin, T* __restrict__ pout, const T* __restrict__ b, int c0, int kc,
-               int tiles_x, int tiles_y, const double* __restrict__ shift_sum, double n_cells) {
+               int tiles_x, int tiles_y, const double* __restrict__ shift_sum, double n_cells, int zero_in) {
     using V = typename Vec2<T>::type;
     constexpr int R = 2 * NSW;                  // LDS ring = number of colour stages
     constexpr int W = TX + 2 * R, H = TY + 2 * R, W2 = W / 2;
@@ -591,8 +601,9 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
     }
     constexpr const T* tag = nullptr;
     auto kclamp = [&](int k) { return k < 0 ? 0 : (k >= nz ? nz - 1 : k); };
+    const int pin_range = zero_in ? 0 : -1;   // zero_in: every load of pin returns 0
     auto fetch_ring = [&](int k, V* v) {
-        const i32x4 r = buf_rsrc(pin + (size_t)kclamp(k) * plane);
+        const i32x4 r = buf_rsrc(pin + (size_t)kclamp(k) * plane, pin_range);
 #pragma unroll
         for (int u = 0; u < NP; u++) v[u] = buf_ld2(r, roff[u], tag);
     };
