@@ -119,6 +119,52 @@ def calibrate_copy(gib=1, reps=5):
     print(json.dumps({"calibrate_copy_bytes_read": 4 * n, "calibrate_copy_bytes_written": 4 * n, "reps": reps}))
 
 
+def _counter_rows(d):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        rows += list(csv.DictReader(open(f)))
+    return rows
+
+
+def write_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, gib=1):
+    """profiles/traffic.json from four rocprofv3 --pmc runs: FETCH_SIZE and
+    WRITE_SIZE over the bench, and over --calibrate-copy.  The counters (KiB per
+    dispatch) are scaled by what they read for the plain copy of known size; the
+    kernel is the FP32 fine-grid smoother (the (variant, grid) group of
+    k_rb_sweep<float, ...> dispatches with the largest total fetch)."""
+    import statistics
+    copy_bytes = gib * (1 << 30)
+
+    def copy_kib(d):
+        v = [float(r["Counter_Value"]) for r in _counter_rows(d) if "copyBuffer" in r["Kernel_Name"]]
+        return statistics.median(v)
+
+    fs = copy_bytes / (copy_kib(cal_fetch_dir) * 1024.0)
+    ws = copy_bytes / (copy_kib(cal_write_dir) * 1024.0)
+
+    def groups(d):
+        g = {}
+        for r in _counter_rows(d):
+            if r["Kernel_Name"].startswith("void mgk::k_rb_sweep<float"):
+                g.setdefault((r["Kernel_Name"].split("(")[0], r["Grid_Size"]), []).append(float(r["Counter_Value"]))
+        return g
+
+    F, W = groups(fetch_dir), groups(write_dir)
+    key = max(F, key=lambda k: sum(F[k]))
+    fetch = statistics.median(F[key]) * 1024.0 * fs
+    write = statistics.median(W[key]) * 1024.0 * ws
+    out = {"class": "smooth_fine", "kernel": key[0].replace("void mgk::", ""), "grid": int(key[1]),
+           "dispatches": len(F[key]), "fetch_bytes": fetch, "write_bytes": write,
+           "bytes_per_launch": fetch + write, "fetch_scale": fs, "write_scale": ws,
+           "source_sha": kernel_source_sha()}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
+
+
 def summarize(d):
     """Markdown summary of rocprofv3 CSV output in directory d (kernel stats,
     per-dispatch durations by grid size, counters per dispatch)."""
@@ -277,6 +323,8 @@ def main():
     ap.add_argument("--graph", type=int, default=1, help="replay each outer iteration as a HIP graph (1) or launch eagerly (0)")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (counter scale)")
     ap.add_argument("--summarize", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
+    ap.add_argument("--traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+                    help="write profiles/traffic.json from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
     ap.add_argument("--batch", action="store_true", help="batched uneven solves through the server")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--serve", action="store_true", help="Poisson-arrival serving sweep")
@@ -286,6 +334,9 @@ def main():
     ap.add_argument("--arena-gb", type=float, default=24.0)
     ap.add_argument("--slots", type=int, default=16)
     args = ap.parse_args()
+    if args.traffic:
+        write_traffic(*args.traffic)
+        return
     if args.summarize:
         summarize(args.summarize)
         return
