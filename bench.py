@@ -320,6 +320,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--inner-m", type=int, default=0, help="FP32 V-cycles per outer iteration (0: library default)")
     ap.add_argument("--graph", type=int, default=1, help="replay each outer iteration as a HIP graph (1) or launch eagerly (0)")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (counter scale)")
     ap.add_argument("--summarize", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
@@ -374,8 +375,9 @@ def main():
     def build(precision, profile=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        kw = {"inner_m": args.inner_m} if args.inner_m else {}
         S = mg.Solver(bx, by, bz, precision=precision, n_coarsest=args.n_coarsest, profile=profile,
-                      graph=args.graph and not profile)
+                      graph=args.graph and not profile, **kw)
         torch.cuda.synchronize()
         return S, (time.perf_counter() - t0) * 1e3
 

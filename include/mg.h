@@ -74,7 +74,7 @@ typedef struct {
     int n_coarsest;  /* halve every dimension while all are even and the largest
                         exceeds n_coarsest (default 4); the coarsest grid must have
                         <= MG_MAX_COARSE_CELLS cells */
-    int inner_m;     /* FP32 V-cycles per FP64 outer iteration (refined mode, default 2) */
+    int inner_m;     /* FP32 V-cycles per FP64 outer iteration (refined mode, default 3) */
     int max_cycles;  /* V-cycles (FP64) or outer iterations (refined), default 100 */
     int profile;     /* nonzero: time every kernel launch with HIP events (stats.kernel_*) */
     int tile;        /* smoother kernel: 0 = automatic (each level's variant is chosen by

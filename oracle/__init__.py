@@ -191,7 +191,7 @@ STATUS = {0: "converged", 1: "not_converged", 2: "diverged", -1: "invalid"}
 
 
 def solve(bx, by, bz, b, p0=None, nu1=2, nu2=2, n_coarsest=4, max_cycles=100, tol=1e-10,
-          precision="fp64", inner_m=2):
+          precision="fp64", inner_m=3):
     """Run the oracle solve.  Returns dict(p, history, cycles, status, gamma, mean_b)."""
     b = _c(b)
     nx, ny, nz = dims_of(b)

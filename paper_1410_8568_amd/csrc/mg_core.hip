@@ -864,7 +864,7 @@ mg_status mg_default_options(mg_options* o) {
     o->nu1 = 2;
     o->nu2 = 2;
     o->n_coarsest = 4;
-    o->inner_m = 2;
+    o->inner_m = 3;
     o->max_cycles = 100;
     o->profile = 0;
     o->tile = 0;

@@ -128,7 +128,7 @@ class MGError(RuntimeError):
         self.status = status
 
 
-def options(precision="fp64", nu1=2, nu2=2, n_coarsest=4, inner_m=2, max_cycles=100, profile=False,
+def options(precision="fp64", nu1=2, nu2=2, n_coarsest=4, inner_m=3, max_cycles=100, profile=False,
             tile=0, graph=False):
     o = Options()
     lib().mg_default_options(ctypes.byref(o))

@@ -249,7 +249,7 @@ def test_config0_equals_direct_solve(oracle_lib):
 
 def test_fp32_refined_reaches_fp64_solution(oracle_lib):
     P, ref = config0_direct()
-    for m in (1, 2):
+    for m in (1, 2, 3):
         r = oracle_lib.solve(P.bx, P.by, P.bz, P.b, tol=1e-10, precision="fp32_refined", inner_m=m)
         assert r["status"] == "converged"
         assert rel(r["p"], ref) < 1e-8
