@@ -331,18 +331,19 @@ struct Hier {
     const T* a[MG_MAX_LEVELS];
 };
 
-template <class T, int TX, int TY, int NSW>
+template <class T, int TX, int TY, int NSW, bool RES = false>
 static void launch_sweep(hipStream_t s, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0, int target,
-                         const double* shift_sum, int zero_in) {
+                         const double* shift_sum, int zero_in, T* rc = nullptr) {
     const int gx = (L.nx + TX - 1) / TX, gy = (L.ny + TY - 1) / TY;
     const int tiles = gx * gy;
     // chunks of >= 8 planes, so the redundant planes at chunk ends stay a small fraction
     int chunks = std::max(1, std::min(std::max(1, L.nz / 8), (target + tiles - 1) / tiles));
-    const int kc = (L.nz + chunks - 1) / chunks;
+    int kc = (L.nz + chunks - 1) / chunks;
+    if (RES && (kc & 1)) kc++;   // the restriction pairs planes 2K, 2K+1 within a chunk
     chunks = (L.nz + kc - 1) / kc;
-    constexpr int NT = (TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2);
-    k_rb_sweep<T, TX, TY, NSW><<<dim3(tiles * chunks), NT, 0, s>>>(L, pin, pout, b, c0, kc, gx, gy, shift_sum,
-                                                                  (double)L.nx * L.ny * L.nz, zero_in);
+    constexpr int NT = (TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES ? 2 : 0));
+    k_rb_sweep<T, TX, TY, NSW, RES><<<dim3(tiles * chunks), NT, 0, s>>>(
+        L, pin, pout, b, c0, kc, gx, gy, shift_sum, (double)L.nx * L.ny * L.nz, zero_in, rc);
 }
 
 // Sweeps done by one pass of fused variant v (1..MG_NUM_TILES).
@@ -380,6 +381,32 @@ static void fused_sweep(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* 
                 launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in);
             break;
     }
+}
+
+// Variants whose two-sweep pass can also form the residual and restrict it
+// (FP32 tiles 64x4, 64x8 and 64x16: 128x8 would need more than 1024 threads).
+template <class T>
+static bool has_restrict_variant(int v) {
+    const int t = (v - 1) >> 1;
+    return sizeof(T) == 4 && v > 0 && (t == 4 || t == 5 || t == 7);
+}
+
+// Two-sweep pass of variant v that also forms the residual of its result and
+// restricts it into rc (the next level's right-hand side); returns false
+// (nothing launched) when v has no such pass.
+template <class T>
+static bool fused_sweep_restrict(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b,
+                                 const double* shift_sum, int zero_in, T* rc) {
+    if constexpr (sizeof(T) == 4) {
+        const int target = ((v - 1) & 1) ? 4096 : 1024;
+        switch ((v - 1) >> 1) {
+            case 4: launch_sweep<T, 64, 4, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc); return true;
+            case 5: launch_sweep<T, 64, 8, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc); return true;
+            case 7: launch_sweep<T, 64, 16, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc); return true;
+            default: return false;
+        }
+    }
+    return false;
 }
 
 template <class T>
@@ -545,10 +572,23 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
     // the current iterate moves between e and tmp as fused passes run
     T* cur = H.e[l];
     T* alt = H.tmp[l];
-    smooth(h, H, l, h->o.nu1, 0, cur, alt, shift_sum, zero_init);
     const LevelDims& c = H.d[l + 1];
-    {
-        Prof pf(h, MG_K_RESTRICT, ((2.0 * d.ncell() + d.nfaces()) + c.ncell()) * sizeof(T));
+    const double restrict_bytes = ((2.0 * d.ncell() + d.nfaces()) + c.ncell()) * sizeof(T);
+    // pre-smoothing; where one fused two-sweep pass is all of it, that pass also
+    // forms the residual and its restriction
+    const int tile = h->tile[l];
+    bool restricted = false;
+    if (alt && has_restrict_variant<T>(tile) && h->o.nu1 == 2) {
+        const double sweep_bytes = 2.0 * (3.0 * d.ncell() + d.nfaces()) * sizeof(T) -
+                                   (zero_init ? (double)d.ncell() * sizeof(T) : 0.0);
+        Prof pf(h, l == 0 ? MG_K_SMOOTH_FINE : MG_K_SMOOTH, sweep_bytes + restrict_bytes);
+        restricted = fused_sweep_restrict<T>(s, tile, H.L[l], cur, alt, H.rhs[l], shift_sum, zero_init ? 1 : 0,
+                                             H.rhs[l + 1]);
+        if (restricted) std::swap(cur, alt);
+    }
+    if (!restricted) smooth(h, H, l, h->o.nu1, 0, cur, alt, shift_sum, zero_init);
+    if (!restricted) {
+        Prof pf(h, MG_K_RESTRICT, restrict_bytes);
         int nb = 0;
         // restricted levels have even nx; FP32 takes 4 cells per thread (16-byte loads) when it can
         bool quad = false;

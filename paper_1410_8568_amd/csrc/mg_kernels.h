@@ -78,6 +78,14 @@ __device__ __forceinline__ float quot(float num, float d) {
 }
 __device__ __forceinline__ double quot(double num, double d) { return num / d; }
 
+// Residual b - (s - d p) of one cell from its neighbour sum s and diagonal d,
+// with the product taken in a fused multiply-add in every kernel that forms it
+// (so all of them agree bit for bit).
+template <class T>
+__device__ __forceinline__ T resid_val(T b, T s, T d, T p) {
+    return b - fma(-d, p, s);
+}
+
 // Neighbour sum s = sum_f beta_f p_nb and diagonal d = sum_f beta_f for cell
 // (i,j,k); out-of-grid neighbours read as 0 (their face coefficient is 0).
 template <class T>
@@ -555,15 +563,19 @@ struct Vec2<double> {
 // With zero_in set, the iterate entering the pass is zero and pin is not read:
 // its loads go through a buffer resource of range 0, which returns 0 (a
 // coarse-grid correction's first smoothing pass; no separate fill).
-template <class T, int TX, int TY, int NSW>
-__global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
+template <class T, int TX, int TY, int NSW, bool RES = false>
+__global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES ? 2 : 0)))
     k_rb_sweep(Lvl<T> L, const T* __restrict__ pin, T* __restrict__ pout, const T* __restrict__ b, int c0, int kc,
-               int tiles_x, int tiles_y, const double* __restrict__ shift_sum, double n_cells, int zero_in) {
+               int tiles_x, int tiles_y, const double* __restrict__ shift_sum, double n_cells, int zero_in,
+               T* __restrict__ rc) {
     using V = typename Vec2<T>::type;
-    constexpr int R = 2 * NSW;                  // LDS ring = number of colour stages
-    constexpr int W = TX + 2 * R, H = TY + 2 * R, W2 = W / 2;
-    constexpr int PW = TX / 2 + R, PH = TY + 2 * (R - 1), NT = PW * PH;
-    constexpr int NS = R + 3;                   // plane slots: R + 2 live, one being refilled
+    constexpr int R = 2 * NSW;                  // number of colour stages
+    constexpr int E = RES ? 1 : 0;              // extra ring for the residual's neighbours
+    constexpr int RXs = R + 2 * E, RYs = R + E; // staged ring (x: whole pairs)
+    constexpr int W = TX + 2 * RXs, H = TY + 2 * RYs, W2 = W / 2;
+    constexpr int PW = TX / 2 + R, PH = TY + 2 * (R - 1 + E), NT = PW * PH;
+    constexpr int NS = R + 3 + E;               // plane slots: R + 2 (+1) live, one being refilled
+    static_assert(!RES || (TX % 2 == 0 && TY % 2 == 0), "restriction needs even tiles");
     constexpr int PL = H * W;                   // elements of a staged plane
     constexpr int NV = H * W2;                  // pairs in a staged plane
     constexpr int NP = (NV + NT - 1) / NT;      // staged pairs per thread
@@ -575,12 +587,13 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
     const int k0 = chunk * kc, k1 = min(nz, k0 + kc);
     const int tid = threadIdx.x;
     const int q = tid % PW, lj = tid / PW;
-    const int ia = i0 - R + 2 * q, gj = j0 - R + 1 + lj;      // first cell of the pair, row
+    const int ia = i0 - R + 2 * q, gj = j0 - (R - 1 + E) + lj;   // first cell of the pair, row
     const int row = lj + 1;                                   // LDS row of this thread
+    const int qq = q + E;                                     // LDS half-row index of its pair
     const bool inpair = ia >= 0 && ia < nx && gj >= 0 && gj < ny;   // nx even: both cells in or both out
     const size_t plane = (size_t)nx * ny;
     const T shift = shift_sum ? (T)(shift_sum[0] / n_cells) : T(0);
-    const int tfirst = k0 - R + 1, tlast = k1 + R - 2;
+    const int tfirst = k0 - R + 1 - E, tlast = k1 + R - 2 + E;
 
     // LDS position of (row r, column c) within a plane: (2r + (c & 1)) * W2 + c / 2.
     // Global loads are unconditional (clamped to a valid address) so the compiler
@@ -594,7 +607,7 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
     for (int u = 0; u < NP; u++) {
         const int v = tid + u * NT;
         const int vi = v % W2, vj = v / W2;
-        const int ii = i0 - R + 2 * vi, jj = j0 - R + vj;
+        const int ii = i0 - RXs + 2 * vi, jj = j0 - RYs + vj;
         rpos[u] = v < NV ? vj * W + vi : -1;
         rin[u] = v < NV && ii >= 0 && ii < nx && jj >= 0 && jj < ny;
         roff[u] = rin[u] ? (uint32_t)(jj * nx + ii) * (uint32_t)sizeof(T) : 0u;
@@ -652,20 +665,22 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
     auto mask_fz = [&](int k, V& f) {
         if (k >= nz) f.x = f.y = T(0);
     };
-    // Ring distance of each cell of the pair: stage h updates the cell when it is
-    // within R - h of the tile (large when the pair is outside the grid).
+    // Ring distance of each cell of the pair (c: LDS column): stage h updates the
+    // cell when it is within R - h (+1 with RES) of the tile (large when the pair
+    // is outside the grid).
     auto ring_dist = [&](int c) {
-        const int dx = max(R - c, c - (R + TX - 1)), dy = max(R - row, row - (R + TY - 1));
+        const int dx = max(RXs - c, c - (RXs + TX - 1)), dy = max(RYs - row, row - (RYs + TY - 1));
         return inpair ? max(max(dx, dy), 0) : 4 * R;
     };
-    const int dist0 = ring_dist(2 * q), dist1 = ring_dist(2 * q + 1);
+    const int dist0 = ring_dist(2 * qq), dist1 = ring_dist(2 * qq + 1);
 
     V ring[NP];
-    if constexpr (sizeof(T) == 4 || NSW == 1) {
+    if constexpr (sizeof(T) == 4 || NSW == 1 || RES) {
         // One step per iteration; the register queues shift by one plane per
         // step (fewer live registers, so more waves fit per CU).
-        FB fq[R + 1];     // fq[h]: x/y faces and b of plane t - h + 1 during step t (fq[0] in flight)
-        V fzq[R + 2];     // fzq[h]: z-faces of plane t - h + 2 during step t (fzq[0] in flight)
+        constexpr int NQ = R + 1 + 2 * E;   // RES keeps two more planes for the residual
+        FB fq[NQ];        // fq[h]: x/y faces and b of plane t - h + 1 during step t (fq[0] in flight)
+        V fzq[NQ + 1];    // fzq[h]: z-faces of plane t - h + 2 during step t (fzq[0] in flight)
         auto lslot = [&](int k) { return (k - tfirst + NS) % NS; };
         fetch_ring(tfirst - 1, ring);
         store_ring(lslot(tfirst - 1), tfirst - 1, ring);
@@ -675,15 +690,48 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
         fetch_fb(tfirst, fq[0]);
         fzq[0] = fetch_fz(tfirst + 1);
         fzq[1] = fetch_fz(tfirst);
-        static_for<1, R + 1>([&](auto sc) { fq[decltype(sc)::value] = fq[0]; });
-        static_for<2, R + 2>([&](auto sc) { fzq[decltype(sc)::value] = fzq[1]; });
-        for (int t = tfirst; t <= tlast; t++) {
-            static_for<0, R>([&](auto hc) {
-                constexpr int h = R - decltype(hc)::value;
+        static_for<1, NQ>([&](auto sc) { fq[decltype(sc)::value] = fq[0]; });
+        static_for<2, NQ + 1>([&](auto sc) { fzq[decltype(sc)::value] = fzq[1]; });
+        // RES: residual r = b - (s - d p) of the tile's cells on plane t - R - 1 (whose
+        // neighbours are final), summed over the x pair, then over the plane pair;
+        // the row pair is added through LDS one step later.
+        __shared__ T red[RES ? PH : 1][RES ? PW : 1];
+        const bool tpair = RES && dist0 == 0 && dist1 == 0;   // a pair of the tile
+        T racc = T(0);
+        auto epilogue = [&](int zr) {
+            if constexpr (RES) {
+                if (zr - 1 >= k0 && ((zr - 1) & 1) && tpair && !(gj & 1))
+                    rc[cidx(ia >> 1, gj >> 1, (zr - 1) >> 1, nx >> 1, ny >> 1)] = T(0.5) * (racc + red[lj + 1][q]);
+                if (zr >= k0 && zr < k1 && tpair) {
+                    const FB& f = fq[R + 2];
+                    const V wz0 = fzq[R + 3], wz1 = fzq[R + 2];
+                    const T* c = sp + lslot(zr) * PL;
+                    const T* cd = sp + lslot(zr - 1) * PL;
+                    const T* cu = sp + lslot(zr + 1) * PL;
+                    const int o0 = 2 * row * W2 + qq, o1 = o0 + W2;   // even and odd cell
+                    const T s0 = stencil_sum(f.fx.x, f.fx.y, f.fy.x, f.fyu.x, wz0.x, wz1.x, c[o1 - 1], c[o1],
+                                             c[o0 - W], c[o0 + W], cd[o0], cu[o0]);
+                    const T d0 = stencil_diag(f.fx.x, f.fx.y, f.fy.x, f.fyu.x, wz0.x, wz1.x);
+                    const T s1 = stencil_sum(f.fx.y, f.fxu, f.fy.y, f.fyu.y, wz0.y, wz1.y, c[o0], c[o0 + 1],
+                                             c[o1 - W], c[o1 + W], cd[o1], cu[o1]);
+                    const T d1 = stencil_diag(f.fx.y, f.fxu, f.fy.y, f.fyu.y, wz0.y, wz1.y);
+                    const T sum = resid_val(f.bb.x, s0, d0, c[o0]) + resid_val(f.bb.y, s1, d1, c[o1]);
+                    if (zr & 1) {
+                        racc += sum;
+                        red[lj][q] = racc;
+                    } else {
+                        racc = sum;
+                    }
+                }
+            }
+        };
+        for (int t = tfirst; t <= tlast + E; t++) {
+            static_for<0, NQ - 1>([&](auto hc) {
+                constexpr int h = NQ - 1 - decltype(hc)::value;
                 fq[h] = fq[h - 1];
             });
-            static_for<0, R + 1>([&](auto hc) {
-                constexpr int h = R + 1 - decltype(hc)::value;
+            static_for<0, NQ>([&](auto hc) {
+                constexpr int h = NQ - decltype(hc)::value;
                 fzq[h] = fzq[h - 1];
             });
             store_ring(lslot(t + 1), t + 1, ring);
@@ -693,15 +741,16 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
             fetch_ring(t + 2, ring);                  // in flight during this step
             fetch_fb(t + 1, fq[0]);
             fzq[0] = fetch_fz(t + 2);
+            epilogue(t - R - 1);
             const int e = (c0 + i0 + gj + t) & 1;
             const int dist = e ? dist1 : dist0;
-            const int oc = (2 * row + e) * W2 + q;                    // the cell
-            const int ol = e ? 2 * row * W2 + q : (2 * row + 1) * W2 + q - 1;
-            const int orr = e ? 2 * row * W2 + q + 1 : (2 * row + 1) * W2 + q;
-            const int opart = (2 * row + (e ^ 1)) * W2 + q;           // its pair partner
+            const int oc = (2 * row + e) * W2 + qq;                   // the cell
+            const int ol = e ? 2 * row * W2 + qq : (2 * row + 1) * W2 + qq - 1;
+            const int orr = e ? 2 * row * W2 + qq + 1 : (2 * row + 1) * W2 + qq;
+            const int opart = (2 * row + (e ^ 1)) * W2 + qq;          // its pair partner
             static_for<1, R + 1>([&](auto hc) {
                 constexpr int h = decltype(hc)::value;
-                constexpr int rg = R - h;                               // this stage's ring width
+                constexpr int rg = R - h + E;                           // this stage's ring width
                 const int z = t - h + 1;
                 const int sz = lslot(z), sd = lslot(z - 1), su = lslot(z + 1);
                 const bool in_z = z >= 0 && z < nz && z >= k0 - rg && z < k1 + rg;
@@ -720,16 +769,24 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2))
                 if constexpr (h < R) {
                     if (in_z && dist <= rg) sp[sz * PL + oc] = vnew;
                     lds_barrier();
-                } else if (in_z && dist <= rg) {
+                } else {
                     // the tile's plane z is final: this cell from stage R, its pair
                     // partner from stage R-1 of the previous step
-                    const T vold = c[opart];
-                    V out;
-                    out.x = e ? vold : vnew;
-                    out.y = e ? vnew : vold;
-                    buf_st2(out, buf_rsrc(pout + (size_t)z * plane), cb);
+                    if (RES && in_z && dist <= rg) sp[sz * PL + oc] = vnew;
+                    if (in_z && dist == 0 && z >= k0 && z < k1) {
+                        const T vold = c[opart];
+                        V out;
+                        out.x = e ? vold : vnew;
+                        out.y = e ? vnew : vold;
+                        buf_st2(out, buf_rsrc(pout + (size_t)z * plane), cb);
+                    }
                 }
             });
+        }
+        if constexpr (RES) {
+            // the row pairs of the last (odd) plane of the chunk
+            lds_barrier();
+            epilogue(tlast + E - R);
         }
     } else {
         // FP64, several sweeps: the loop is unrolled by NS steps, so every queue
@@ -872,7 +929,7 @@ __global__ void __launch_bounds__(CBX* CBY) k_resid_col(Lvl<T> L, const T* __res
             const T s = stencil_sum(cur.wx0, cur.wx1, cur.wy0, cur.wy1, wz0, cur.wz1, cur.pw, cur.pe, cur.ps,
                                     cur.pn, pbelow, pabove);
             const T d = stencil_diag(cur.wx0, cur.wx1, cur.wy0, cur.wy1, wz0, cur.wz1);
-            const T r = cur.b - (s - d * cur.p);
+            const T r = resid_val(cur.b, s, d, cur.p);
             if (MODE == 1) r32[(size_t)k * plane + col] = (float)((double)r * inv_s);
             a += (double)r * (double)r;
             q += (double)cur.p;
@@ -1002,7 +1059,7 @@ __device__ __forceinline__ void cells_residual(const Cells1<T, NC>& c, const T (
         const T s = stencil_sum(c.fx[e], w1, c.fy[e], c.fyu[e], c.fz[e], up.fz[e], pw, pe, c.ps[e], c.pn[e], pb[e],
                                 up.p[e]);
         const T d = stencil_diag(c.fx[e], w1, c.fy[e], c.fyu[e], c.fz[e], up.fz[e]);
-        r[e] = c.b[e] - (s - d * c.p[e]);
+        r[e] = resid_val(c.b[e], s, d, c.p[e]);
     }
 }
 
