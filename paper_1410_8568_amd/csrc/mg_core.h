@@ -65,7 +65,8 @@ struct mg_handle {
     int* flag = nullptr;
     hipStream_t stream = nullptr;
     double* host = nullptr;  // pinned host copy of device scalars
-    int tile[MG_MAX_LEVELS];  // smoother variant per level
+    int tile[MG_MAX_LEVELS];   // smoother variant per level
+    int rtile[MG_MAX_LEVELS];  // variant of the fused pre-smoothing + restriction pass (0: none)
     // profiling
     struct Rec {
         int cls;

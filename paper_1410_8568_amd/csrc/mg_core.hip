@@ -216,7 +216,10 @@ static void prof_collect(mg_handle* h) {
 // ------------------------------------------------------------------ setup
 
 template <class T>
-static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b, int* choice);
+static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b, T* rc, int* choice,
+                            int* rchoice);
+template <class T>
+static bool has_restrict_variant(int v);
 
 static void bind(mg_handle* h) {
     const Layout& L = h->L;
@@ -284,23 +287,29 @@ mg_status setup_impl(mg_handle* h, const double* bx, const double* by, const dou
         }
         HIPCHK(hipGetLastError());
     }
-    // smoother variant per level
-    for (int l = 0; l < MG_MAX_LEVELS; l++) h->tile[l] = 0;
+    // smoother variant (and fused pre-smoothing + restriction variant) per level
+    const bool f32 = h->o.precision == MG_FP32_REFINED;
+    for (int l = 0; l < MG_MAX_LEVELS; l++) h->tile[l] = h->rtile[l] = 0;
     for (int l = 0; l + 1 < L.nlev; l++) {
         if (h->o.tile != 0) {
             h->tile[l] = h->o.tile;
+            h->rtile[l] = (h->o.nu1 == 2 && (f32 ? has_restrict_variant<float>(h->o.tile)
+                                                 : has_restrict_variant<double>(h->o.tile)))
+                              ? h->o.tile
+                              : 0;
             continue;
         }
         const LevelDims& d = L.d[l];
         mg_status r;
-        if (h->o.precision == MG_FP32_REFINED) {
+        if (f32) {
             Lvl<float> lv{d.nx, d.ny, d.nz, h->fbx[l], h->fby[l], h->fbz[l]};
-            r = tune_level<float>(h, lv, h->fe[l], h->ftmp[l], h->frhs[l], &h->tile[l]);
+            r = tune_level<float>(h, lv, h->fe[l], h->ftmp[l], h->frhs[l], h->frhs[l + 1], &h->tile[l],
+                                  &h->rtile[l]);
         } else {
             Lvl<double> lv{d.nx, d.ny, d.nz, h->bx[l], h->by[l], h->bz[l]};
             double* pin = l == 0 ? h->bbar : h->e[l];
             double* b = l == 0 ? h->bbar : h->rhs[l];
-            r = tune_level<double>(h, lv, pin, h->tmp[l], b, &h->tile[l]);
+            r = tune_level<double>(h, lv, pin, h->tmp[l], b, h->rhs[l + 1], &h->tile[l], &h->rtile[l]);
         }
         if (r != MG_OK) return r;
     }
@@ -416,17 +425,36 @@ static void ref_sweep(hipStream_t s, const Lvl<T>& L, T* p, const T* b, int c0) 
     k_rb_half<T><<<g, blk, 0, s>>>(L, p, b, 1 - c0);
 }
 
+// Residual of level L restricted into rc (the next level's right-hand side),
+// as a separate pass: 4 cells per thread in FP32 when nx allows, else 2.
+template <class T>
+static void launch_restrict(hipStream_t s, const Lvl<T>& L, const T* p, const T* b, T* rc) {
+    int nb = 0;
+    if constexpr (sizeof(T) == 4) {
+        if (L.nx % 4 == 0) {
+            const ColGrid G = zgrid(L.nx / 4, L.ny, L.nz, true, &nb);
+            k_resid_restrict_cells<T, 4><<<nb, CBX * CBY, 0, s>>>(L, p, b, G, rc);
+            return;
+        }
+    }
+    const ColGrid G = zgrid(L.nx / 2, L.ny, L.nz, true, &nb);
+    k_resid_restrict_cells<T, 2><<<nb, CBX * CBY, 0, s>>>(L, p, b, G, rc);
+}
+
 // ------------------------------------------------------------------ smoother tuning
 //
 // For every smoothed level the variant with the shortest measured sweep is
-// chosen at setup (each variant: one warm-up and three timed sweeps on the
-// level's own scratch buffers, zero-filled), and remembered per (precision,
-// grid size) for the life of the process and, when MG_TUNE_CACHE names a file,
-// across processes (one JSON object per line).
+// chosen at setup (each variant: one warm-up and three timed passes on the
+// level's own scratch buffers, zero-filled).  Where nu1 = 2 and the level has
+// fused pre-smoothing + restriction variants, each is timed against two sweeps
+// of the chosen variant plus the separate restriction, and the fastest way is
+// kept.  Choices are remembered per (precision, grid size) for the life of the
+// process and, when MG_TUNE_CACHE names a file, across processes (one JSON
+// object per line).
 
 namespace {
 std::mutex g_tune_mu;
-std::map<std::array<int, 4>, int> g_tune;
+std::map<std::array<int, 4>, std::pair<int, int>> g_tune;
 bool g_tune_loaded = false;
 
 void tune_load_locked() {
@@ -438,35 +466,39 @@ void tune_load_locked() {
     if (!f) return;
     char line[256];
     while (fgets(line, sizeof line, f)) {
-        int pr, x, y, z, v;
-        if (sscanf(line, "{\"bytes\": %d, \"nx\": %d, \"ny\": %d, \"nz\": %d, \"variant\": %d}", &pr, &x, &y, &z,
-                   &v) == 5 &&
-            v >= -1 && v <= MG_NUM_TILES && v != 0)
-            g_tune[{pr, x, y, z}] = v;
+        int pr, x, y, z, v, rv;
+        if (sscanf(line, "{\"bytes\": %d, \"nx\": %d, \"ny\": %d, \"nz\": %d, \"variant\": %d, \"restrict\": %d}", &pr,
+                   &x, &y, &z, &v, &rv) == 6 &&
+            v >= -1 && v <= MG_NUM_TILES && v != 0 && rv >= 0 && rv <= MG_NUM_TILES)
+            g_tune[{pr, x, y, z}] = {v, rv};
     }
     fclose(f);
 }
 
-void tune_store_locked(const std::array<int, 4>& k, int v) {
-    g_tune[k] = v;
+void tune_store_locked(const std::array<int, 4>& k, int v, int rv) {
+    g_tune[k] = {v, rv};
     const char* path = getenv("MG_TUNE_CACHE");
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "{\"bytes\": %d, \"nx\": %d, \"ny\": %d, \"nz\": %d, \"variant\": %d}\n", k[0], k[1], k[2], k[3], v);
+    fprintf(f, "{\"bytes\": %d, \"nx\": %d, \"ny\": %d, \"nz\": %d, \"variant\": %d, \"restrict\": %d}\n", k[0], k[1],
+            k[2], k[3], v, rv);
     fclose(f);
 }
 }  // namespace
 
 template <class T>
-static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b, int* choice) {
+static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b, T* rc, int* choice,
+                            int* rchoice) {
+    // the cached fused-restriction choice assumes nu1 = 2; other nu1 never fuse
     const std::array<int, 4> key{(int)sizeof(T), L.nx, L.ny, L.nz};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
         auto it = g_tune.find(key);
         if (it != g_tune.end()) {
-            *choice = it->second;
+            *choice = it->second.first;
+            *rchoice = h->o.nu1 == 2 ? it->second.second : 0;
             return MG_OK;
         }
     }
@@ -477,16 +509,7 @@ static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    float best = 1e30f;
-    int bestv = -1;
-    for (int v = -1; v <= MG_NUM_TILES; v++) {
-        if (v == 0 || (v > 0 && !variant_native<T>(v))) continue;
-        auto run = [&]() {
-            if (v < 0)
-                ref_sweep<T>(s, L, pin, b, 0);
-            else
-                fused_sweep<T>(s, v, L, pin, pout, b, 0);
-        };
+    auto time_ms = [&](auto&& run) {
         run();
         float tmin = 1e30f;
         for (int rep = 0; rep < 3; rep++) {
@@ -498,18 +521,46 @@ static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b
             (void)hipEventElapsedTime(&ms, e0, e1);
             tmin = std::min(tmin, ms);
         }
-        if (v > 0) tmin /= sweeps_per_pass(v);
-        if (tmin < best) {
-            best = tmin;
+        return tmin;
+    };
+    float best = 1e30f;
+    int bestv = -1;
+    for (int v = -1; v <= MG_NUM_TILES; v++) {
+        if (v == 0 || (v > 0 && !variant_native<T>(v))) continue;
+        float t = time_ms([&]() {
+            if (v < 0)
+                ref_sweep<T>(s, L, pin, b, 0);
+            else
+                fused_sweep<T>(s, v, L, pin, pout, b, 0);
+        });
+        if (v > 0) t /= sweeps_per_pass(v);
+        if (t < best) {
+            best = t;
             bestv = v;
+        }
+    }
+    // fused pre-smoothing + restriction against two sweeps plus the separate pass
+    int bestr = 0;
+    bool any = false;
+    for (int v = 1; v <= MG_NUM_TILES; v++) any = any || has_restrict_variant<T>(v);
+    if (any) {
+        float rbest = 2.0f * best + time_ms([&]() { launch_restrict<T>(s, L, pin, b, rc); });
+        for (int v = 1; v <= MG_NUM_TILES; v++) {
+            if (!has_restrict_variant<T>(v)) continue;
+            const float t = time_ms([&]() { fused_sweep_restrict<T>(s, v, L, pin, pout, b, nullptr, 0, rc); });
+            if (t < rbest) {
+                rbest = t;
+                bestr = v;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIPCHK(hipGetLastError());
     *choice = bestv;
+    *rchoice = h->o.nu1 == 2 ? bestr : 0;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    tune_store_locked(key, bestv);
+    tune_store_locked(key, bestv, bestr);
     return MG_OK;
 }
 
@@ -574,35 +625,19 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
     T* alt = H.tmp[l];
     const LevelDims& c = H.d[l + 1];
     const double restrict_bytes = ((2.0 * d.ncell() + d.nfaces()) + c.ncell()) * sizeof(T);
-    // pre-smoothing; where one fused two-sweep pass is all of it, that pass also
-    // forms the residual and its restriction
-    const int tile = h->tile[l];
-    bool restricted = false;
-    if (alt && has_restrict_variant<T>(tile) && h->o.nu1 == 2) {
+    // pre-smoothing; where the level's tuning chose the fused pass (one two-sweep
+    // pass is all of it), that pass also forms the residual and its restriction
+    const int rtile = alt ? h->rtile[l] : 0;
+    if (rtile > 0) {
         const double sweep_bytes = 2.0 * (3.0 * d.ncell() + d.nfaces()) * sizeof(T) -
                                    (zero_init ? (double)d.ncell() * sizeof(T) : 0.0);
         Prof pf(h, l == 0 ? MG_K_SMOOTH_FINE : MG_K_SMOOTH, sweep_bytes + restrict_bytes);
-        restricted = fused_sweep_restrict<T>(s, tile, H.L[l], cur, alt, H.rhs[l], shift_sum, zero_init ? 1 : 0,
-                                             H.rhs[l + 1]);
-        if (restricted) std::swap(cur, alt);
-    }
-    if (!restricted) smooth(h, H, l, h->o.nu1, 0, cur, alt, shift_sum, zero_init);
-    if (!restricted) {
+        fused_sweep_restrict<T>(s, rtile, H.L[l], cur, alt, H.rhs[l], shift_sum, zero_init ? 1 : 0, H.rhs[l + 1]);
+        std::swap(cur, alt);
+    } else {
+        smooth(h, H, l, h->o.nu1, 0, cur, alt, shift_sum, zero_init);
         Prof pf(h, MG_K_RESTRICT, restrict_bytes);
-        int nb = 0;
-        // restricted levels have even nx; FP32 takes 4 cells per thread (16-byte loads) when it can
-        bool quad = false;
-        if constexpr (sizeof(T) == 4) {
-            if (d.nx % 4 == 0) {
-                const ColGrid G = zgrid(d.nx / 4, d.ny, d.nz, true, &nb);
-                k_resid_restrict_cells<T, 4><<<nb, CBX * CBY, 0, s>>>(H.L[l], cur, H.rhs[l], G, H.rhs[l + 1]);
-                quad = true;
-            }
-        }
-        if (!quad) {
-            const ColGrid G = zgrid(d.nx / 2, d.ny, d.nz, true, &nb);
-            k_resid_restrict_cells<T, 2><<<nb, CBX * CBY, 0, s>>>(H.L[l], cur, H.rhs[l], G, H.rhs[l + 1]);
-        }
+        launch_restrict<T>(s, H.L[l], cur, H.rhs[l], H.rhs[l + 1]);
     }
     vcycle(h, H, l + 1, nullptr, true);   // the coarse correction starts from zero
     {
