@@ -90,7 +90,13 @@ struct Prof {
     ~Prof();
 };
 
-mg_status setup_impl(mg_handle* h, const double* bx, const double* by, const double* bz);
+// Setup in two halves: setup_launch enqueues the hierarchy build (and tunes
+// the smoother, which synchronises, for grid sizes not tuned before) and the
+// copy of the validation flags to the pinned host block; setup_finish checks
+// them once h->stream has been synchronised.
+mg_status setup_launch(mg_handle* h, const double* bx, const double* by, const double* bz);
+mg_status setup_finish(mg_handle* h);
+inline int* setup_flags(mg_handle* h) { return reinterpret_cast<int*>(h->host + 14); }
 mg_status solve_impl(mg_handle* h, const double* rhs, double* p, double tol, mg_stats* st);
 
 // Solve as a state machine, so that a scheduler can interleave many problems.
@@ -109,7 +115,8 @@ struct SolveState {
     bool graph_failed = false;
     std::chrono::steady_clock::time_point t0;
 };
-mg_status solve_begin(SolveState& S);             // blocking: projection + initial residual
+mg_status solve_begin_launch(SolveState& S);      // asynchronous: projection + initial residual
+mg_status solve_begin_finish(SolveState& S);      // after h->stream is synchronised
 mg_status solve_launch_iteration(SolveState& S);  // asynchronous: one (outer) iteration
 void solve_after_sync(SolveState& S);             // after h->stream is synchronised
 bool solve_running(const SolveState& S);

@@ -252,7 +252,7 @@ static void bind(mg_handle* h) {
     h->flag = (int*)(w + L.flag);
 }
 
-mg_status setup_impl(mg_handle* h, const double* bx, const double* by, const double* bz) {
+mg_status setup_launch(mg_handle* h, const double* bx, const double* by, const double* bz) {
     bind(h);
     const Layout& L = h->L;
     hipStream_t s = h->stream;
@@ -313,9 +313,13 @@ mg_status setup_impl(mg_handle* h, const double* bx, const double* by, const dou
         }
         if (r != MG_OK) return r;
     }
-    int flags[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(flags, h->flag, sizeof flags, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    // validation flags land in the pinned host block; setup_finish reads them
+    HIPCHK(hipMemcpyAsync(setup_flags(h), h->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    return MG_OK;
+}
+
+mg_status setup_finish(mg_handle* h) {
+    const int* flags = setup_flags(h);
     if (flags[0]) {
         set_error(std::to_string(flags[0]) + " interior face coefficient(s) not finite and > 0");
         return MG_E_INVALID;
@@ -696,8 +700,9 @@ static int launch_resid(hipStream_t s, const Lvl<double>& L, const double* p, co
     return nb;
 }
 
-// Step 1 (blocking): project b, initial residual, history[0].
-mg_status solve_begin(SolveState& S) {
+// Step 1a (asynchronous): project b, initial residual, and the copy of the
+// scalars (sum b, sum b^2, sum b_bar, sum b_bar^2, sum r^2, sum p) to h->host.
+mg_status solve_begin_launch(SolveState& S) {
     mg_handle* h = S.h;
     S.t0 = std::chrono::steady_clock::now();
     prof_reset(h);
@@ -721,21 +726,6 @@ mg_status solve_begin(SolveState& S) {
         k_project<<<g0, blk, 0, s>>>(S.rhs, h->bbar, h->scal, d0.nx, d0.ny, d0.nz, h->part);
     }
     finish(h, nb0, 2);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(h->host, h->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    S.st.mean_b = h->host[0] / N;
-    S.norm_b = std::sqrt(h->host[3]);
-    S.st.norm_b = S.norm_b;
-    if (S.norm_b == 0.0) {
-        k_fill<double><<<lin_grid(d0.ncell()), 256, 0, s>>>(S.p, d0.ncell(), 0.0);
-        HIPCHK(hipStreamSynchronize(s));
-        S.st.nhist = 1;
-        S.st.history[0] = 0.0;
-        S.rho0 = S.rho = 0.0;
-        S.status = MG_OK;
-        return MG_OK;
-    }
     const double resid_bytes = (2.0 * N + d0.nfaces()) * 8.0;
     int nbz = 0;
     if (f32) {
@@ -750,13 +740,33 @@ mg_status solve_begin(SolveState& S) {
     finish(h, nbz, 4);
     S.project = true;  // scal[5] now holds sum(p); p is made mean-zero lazily
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(h->host, h->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    S.rho0 = S.rho = std::sqrt(h->host[0]) / S.norm_b;
+    HIPCHK(hipMemcpyAsync(h->host, h->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    return MG_OK;
+}
+
+// Step 1b (after h->stream is synchronised): history[0], status.  A zero
+// right-hand side gives p = 0 (one blocking fill).
+mg_status solve_begin_finish(SolveState& S) {
+    mg_handle* h = S.h;
+    const LevelDims& d0 = h->L.d[0];
+    const double N = (double)d0.ncell();
+    S.st.mean_b = h->host[0] / N;
+    S.norm_b = std::sqrt(h->host[3]);
+    S.st.norm_b = S.norm_b;
+    if (S.norm_b == 0.0) {
+        k_fill<double><<<lin_grid(d0.ncell()), 256, 0, h->stream>>>(S.p, d0.ncell(), 0.0);
+        HIPCHK(hipStreamSynchronize(h->stream));
+        S.project = false;
+        S.st.nhist = 1;
+        S.st.history[0] = 0.0;
+        S.rho0 = S.rho = 0.0;
+        S.status = MG_OK;
+        return MG_OK;
+    }
+    S.rho0 = S.rho = std::sqrt(h->host[4]) / S.norm_b;
     S.st.history[0] = S.rho0;
     S.st.nhist = 1;
     S.status = S.rho0 <= S.tol ? MG_OK : MG_E_NOT_CONVERGED;
-    if (S.status == MG_E_NOT_CONVERGED && S.it >= h->o.max_cycles) S.status = MG_E_NOT_CONVERGED;
     return MG_OK;
 }
 
@@ -903,7 +913,9 @@ mg_status solve_impl(mg_handle* h, const double* rhs, double* p, double tol, mg_
     S.rhs = rhs;
     S.p = p;
     S.tol = tol;
-    mg_status r = solve_begin(S);
+    mg_status r = solve_begin_launch(S);
+    if (r == MG_OK) r = hipStreamSynchronize(h->stream) == hipSuccess ? MG_OK : MG_E_HIP;
+    if (r == MG_OK) r = solve_begin_finish(S);
     if (r != MG_OK) return r;
     while (solve_running(S)) {
         r = solve_launch_iteration(S);
@@ -992,7 +1004,9 @@ mg_status mg_setup(const mg_grid* g, const mg_options* o, const double* bx, cons
             mg_destroy(h);
             return MG_E_HIP;
         }
-        r = setup_impl(h, bx, by, bz);
+        r = setup_launch(h, bx, by, bz);
+        if (r == MG_OK) r = hipStreamSynchronize(h->stream) == hipSuccess ? MG_OK : MG_E_HIP;
+        if (r == MG_OK) r = setup_finish(h);
         if (r != MG_OK) {
             mg_destroy(h);
             return r;

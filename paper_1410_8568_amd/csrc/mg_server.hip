@@ -2,9 +2,12 @@
 //
 // Requests arrive through mg_batch_submit from any thread.  A scheduler thread
 // admits them in arrival order as soon as (a) a slot is free and (b) their
-// workspace fits in the free part of the caller's HBM arena (first-fit), builds
-// their hierarchy in place (it stays resident until the request finishes) and
-// then advances every resident problem one outer iteration at a time.  Each
+// workspace fits in the free part of the caller's HBM arena (first-fit),
+// enqueues the build of their hierarchy in place (it stays resident until the
+// request finishes) and the initial residual, and then advances every resident
+// problem one outer iteration at a time.  The scheduler never blocks on a
+// problem's stream (only smoother tuning, on the first problem of a new grid
+// size, synchronises).  Each
 // slot has its own HIP stream, so iterations of different problems overlap on
 // the device; a problem whose iteration has completed is tested for
 // convergence and relaunched immediately, without waiting for the others, and
@@ -39,6 +42,7 @@ struct Job {
     mg_handle* h = nullptr;
     SolveState S;
     hipEvent_t ev = nullptr;
+    bool begin_pending = false;   // setup and the initial residual are in flight
     JobState state = QUEUED;
     mg_result result;
 };
@@ -87,8 +91,10 @@ void complete(mg_server* sv, Job* j, int status) {
     sv->alloc.release(j->off, j->bytes);
 }
 
-// Build the hierarchy and start the solve for an admitted job (scheduler thread).
-// Returns true if the job is running (needs iterations).
+// Enqueue the hierarchy build and the initial residual of an admitted job
+// (scheduler thread) and record the slot's event after them; the scheduler
+// finishes the start once the event has completed.  Returns true if the job is
+// in flight.
 bool start_job(mg_server* sv, Job* j) {
     j->result.start_ms = sv->now_ms();
     mg_handle* h = new mg_handle();
@@ -106,7 +112,7 @@ bool start_job(mg_server* sv, Job* j) {
         return false;
     }
     j->h = h;
-    mg_status r = setup_impl(h, j->req.bx, j->req.by, j->req.bz);
+    mg_status r = setup_launch(h, j->req.bx, j->req.by, j->req.bz);
     if (r != MG_OK) {
         complete(sv, j, r);
         return false;
@@ -116,16 +122,13 @@ bool start_job(mg_server* sv, Job* j) {
     j->S.rhs = j->req.rhs;
     j->S.p = j->req.p;
     j->S.tol = j->req.tol;
-    r = solve_begin(j->S);
-    if (r != MG_OK) {
-        complete(sv, j, r);
+    r = solve_begin_launch(j->S);
+    j->ev = sv->events[j->slot];
+    if (r != MG_OK || hipEventRecord(j->ev, h->stream) != hipSuccess) {
+        complete(sv, j, r != MG_OK ? r : MG_E_HIP);
         return false;
     }
-    if (!solve_running(j->S)) {
-        solve_end(j->S, &j->result.stats);
-        complete(sv, j, j->S.status);
-        return false;
-    }
+    j->begin_pending = true;
     return true;
 }
 
@@ -165,14 +168,8 @@ void scheduler(mg_server* sv) {
                 admitted.push_back(j);
             }
         }
-        for (Job* j : admitted) {
-            if (start_job(sv, j)) {
-                if (launch(sv, j))
-                    sv->active.push_back(j);
-                else
-                    complete(sv, j, MG_E_HIP);
-            }
-        }
+        for (Job* j : admitted)
+            if (start_job(sv, j)) sv->active.push_back(j);
         // ---- advance every resident problem whose iteration has finished
         bool progressed = !admitted.empty();
         for (size_t q = 0; q < sv->active.size();) {
@@ -186,6 +183,25 @@ void scheduler(mg_server* sv) {
             if (e != hipSuccess) {
                 complete(sv, j, MG_E_HIP);
                 sv->active.erase(sv->active.begin() + q);
+                continue;
+            }
+            if (j->begin_pending) {
+                j->begin_pending = false;
+                mg_status r = setup_finish(j->h);
+                if (r == MG_OK) r = solve_begin_finish(j->S);
+                if (r != MG_OK) {
+                    complete(sv, j, r);
+                    sv->active.erase(sv->active.begin() + q);
+                } else if (!solve_running(j->S)) {
+                    solve_end(j->S, &j->result.stats);
+                    complete(sv, j, j->S.status);
+                    sv->active.erase(sv->active.begin() + q);
+                } else if (!launch(sv, j)) {
+                    complete(sv, j, MG_E_HIP);
+                    sv->active.erase(sv->active.begin() + q);
+                } else {
+                    q++;
+                }
                 continue;
             }
             solve_after_sync(j->S);
