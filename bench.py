@@ -131,13 +131,17 @@ def _counter_rows(d):
 def write_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, gib=1):
     """profiles/traffic.json from four rocprofv3 --pmc runs: FETCH_SIZE and
     WRITE_SIZE over the bench, and over --calibrate-copy.  The counters (KiB per
-    dispatch) are scaled by what they read for the plain copy of known size; the
-    kernel is the FP32 fine-grid smoother (the (variant, grid) group of
-    k_rb_sweep<float, ...> dispatches with the largest total fetch)."""
-    import statistics
+    dispatch) are scaled by what they read for the plain copy of known size.  The
+    kernel class is the FP32 fine-grid smoother: among the k_rb_sweep<float, ...>
+    dispatches of the solves (from the first residual pass on; the setup's
+    tuning runs come before), every dispatch whose fetch is at least 40% of the
+    largest (the finest level; the next level moves 8x less), fused-restriction
+    and plain passes alike, as the bench's roofline averages over both.  Dispatches of the two runs are
+    paired by their order within each (kernel, grid) group."""
     copy_bytes = gib * (1 << 30)
 
     def copy_kib(d):
+        import statistics
         v = [float(r["Counter_Value"]) for r in _counter_rows(d) if "copyBuffer" in r["Kernel_Name"]]
         return statistics.median(v)
 
@@ -145,19 +149,28 @@ def write_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, gib=1):
     ws = copy_bytes / (copy_kib(cal_write_dir) * 1024.0)
 
     def groups(d):
+        # dispatches from the first solve on (the setup's smoother tuning comes before it)
+        rows = sorted(_counter_rows(d), key=lambda r: int(r["Dispatch_Id"]))
+        first = min(int(r["Dispatch_Id"]) for r in rows if r["Kernel_Name"].startswith("void mgk::k_resid_cells"))
         g = {}
-        for r in _counter_rows(d):
-            if r["Kernel_Name"].startswith("void mgk::k_rb_sweep<float"):
+        for r in rows:
+            if int(r["Dispatch_Id"]) >= first and r["Kernel_Name"].startswith("void mgk::k_rb_sweep<float"):
                 g.setdefault((r["Kernel_Name"].split("(")[0], r["Grid_Size"]), []).append(float(r["Counter_Value"]))
         return g
 
     F, W = groups(fetch_dir), groups(write_dir)
-    key = max(F, key=lambda k: sum(F[k]))
-    fetch = statistics.median(F[key]) * 1024.0 * fs
-    write = statistics.median(W[key]) * 1024.0 * ws
-    out = {"class": "smooth_fine", "kernel": key[0].replace("void mgk::", ""), "grid": int(key[1]),
-           "dispatches": len(F[key]), "fetch_bytes": fetch, "write_bytes": write,
-           "bytes_per_launch": fetch + write, "fetch_scale": fs, "write_scale": ws,
+    top = max(max(v) for v in F.values())
+    fetch, write, kernels = [], [], set()
+    for k, fv in F.items():
+        wv = W.get(k, [])
+        for i, f in enumerate(fv):
+            if f >= 0.4 * top and i < len(wv):
+                fetch.append(f * 1024.0 * fs)
+                write.append(wv[i] * 1024.0 * ws)
+                kernels.add(k[0].replace("void mgk::", ""))
+    out = {"class": "smooth_fine", "kernels": sorted(kernels), "dispatches": len(fetch),
+           "fetch_bytes": sum(fetch) / len(fetch), "write_bytes": sum(write) / len(write),
+           "bytes_per_launch": (sum(fetch) + sum(write)) / len(fetch), "fetch_scale": fs, "write_scale": ws,
            "source_sha": kernel_source_sha()}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
