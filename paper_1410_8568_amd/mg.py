@@ -244,6 +244,7 @@ class Solver:
         if getattr(self, "h", None):
             lib().mg_destroy(self.h)
             self.h = None
+        self.ws = None   # release the workspace (the hierarchy lived in it)
 
     def __del__(self):
         try:
