@@ -83,7 +83,10 @@ typedef struct {
                         names a file, in that JSON-lines file), -1 = reference
                         one-colour-per-pass kernels on every level, 1..MG_NUM_TILES = one fixed
                         variant of the fused red-black sweep on every level that has a
-                        ping-pong buffer.  Every choice gives bit-identical results. */
+                        ping-pong buffer.  With nu1 = 2 in refined mode, a level's
+                        pre-smoothing pass may also form and restrict the residual (chosen by
+                        the same timing; always, for a fixed variant that has such a pass).
+                        Every choice gives bit-identical results. */
     int graph;       /* nonzero: capture one iteration's launches into a hipGraph on the first
                         iteration of a solve and replay it for the others (fewer host launches;
                         identical results).  Ignored when profile is set.  The server always
