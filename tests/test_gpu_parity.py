@@ -167,7 +167,10 @@ def test_error_paths():
 def test_fused_sweep_tiles_bit_identical(precision, n):
     """The fused red-black sweep (halo recomputed per tile, chunked in z) gives
     exactly the same iterates as the one-colour-per-pass reference kernels, for
-    every tile shape, including ragged tiles and chunks."""
+    every tile shape, including ragged tiles and chunks.  This also covers the
+    zero-input first pass of each coarse correction (the reference fills instead)
+    and, in FP32 for the tiles that have it, the pre-smoothing pass that forms and
+    restricts the residual itself (the reference restricts in a separate pass)."""
     from paper_1410_8568_amd import mg
     P = ragged_problem(n, seed=5)
     ref_p, ref_st = gpu_solve(P, precision=precision, tol=1e-10, tile=-1)
