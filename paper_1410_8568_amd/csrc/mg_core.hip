@@ -396,12 +396,13 @@ static void fused_sweep(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* 
     }
 }
 
-// Variants whose two-sweep pass can also form the residual and restrict it
-// (FP32 tiles 64x4, 64x8 and 64x16: 128x8 would need more than 1024 threads).
+// Variants whose two-sweep pass can also form the residual and restrict it:
+// tiles 64x4 and 64x8, and 64x16 in FP32 (128x8 would need more than 1024
+// threads; an FP64 64x16 pass would not fit its registers).
 template <class T>
 static bool has_restrict_variant(int v) {
     const int t = (v - 1) >> 1;
-    return sizeof(T) == 4 && v > 0 && (t == 4 || t == 5 || t == 7);
+    return v > 0 && (t == 4 || t == 5 || (sizeof(T) == 4 && t == 7));
 }
 
 // Two-sweep pass of variant v that also forms the residual of its result and
@@ -410,16 +411,18 @@ static bool has_restrict_variant(int v) {
 template <class T>
 static bool fused_sweep_restrict(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b,
                                  const double* shift_sum, int zero_in, T* rc) {
-    if constexpr (sizeof(T) == 4) {
-        const int target = ((v - 1) & 1) ? 4096 : 1024;
-        switch ((v - 1) >> 1) {
-            case 4: launch_sweep<T, 64, 4, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc); return true;
-            case 5: launch_sweep<T, 64, 8, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc); return true;
-            case 7: launch_sweep<T, 64, 16, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc); return true;
-            default: return false;
-        }
+    const int target = ((v - 1) & 1) ? 4096 : 1024;
+    switch ((v - 1) >> 1) {
+        case 4: launch_sweep<T, 64, 4, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc); return true;
+        case 5: launch_sweep<T, 64, 8, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc); return true;
+        case 7:
+            if constexpr (sizeof(T) == 4) {
+                launch_sweep<T, 64, 16, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc);
+                return true;
+            }
+            return false;
+        default: return false;
     }
-    return false;
 }
 
 template <class T>
