@@ -67,6 +67,8 @@ def lib():
         L.og_hierarchy_level.restype = i
         L.og_solve.argtypes = [i, i, i, _D, _D, _D, _D, _D, ctypes.POINTER(OgOpts), _D, _I, _D, _D]
         L.og_solve.restype = i
+        L.og_divergence.argtypes = [i, i, i, _D, _D, _D, ctypes.c_double, _D]
+        L.og_correct_velocity.argtypes = [i, i, i, _D, _D, _D, _D, ctypes.c_double, _D, _D, _D]
         L.og_num_threads.restype = i
         L.og_last_timing.argtypes = [_D, _D]
         _lib = L
@@ -207,6 +209,44 @@ def solve(bx, by, bz, b, p0=None, nu1=2, nu2=2, n_coarsest=4, max_cycles=100, to
                         _p(hist), ctypes.byref(ncyc), ctypes.byref(mean_b), ctypes.byref(gamma))
     return dict(p=p, history=hist[:ncyc.value + 1].copy(), cycles=ncyc.value,
                 status=STATUS[rc], gamma=gamma.value, mean_b=mean_b.value)
+
+
+def _faces_dims(u, v, w):
+    nz, ny, nxp = u.shape
+    nx = nxp - 1
+    assert v.shape == (nz, ny + 1, nx) and w.shape == (nz + 1, ny, nx), (u.shape, v.shape, w.shape)
+    return nx, ny, nz
+
+
+def divergence(u, v, w, scale):
+    """Right-hand side of the projection step: b = scale * sum_d (u_d upper - u_d lower),
+    scale = h / dt (Sec. 2.2 with eqs. 9-10; see og_divergence)."""
+    u, v, w = _c(u), _c(v), _c(w)
+    nx, ny, nz = _faces_dims(u, v, w)
+    b = np.empty((nz, ny, nx))
+    lib().og_divergence(nx, ny, nz, _p(u), _p(v), _p(w), float(scale), _p(b))
+    return b
+
+
+def correct_velocity(bx, by, bz, p, u, v, w, scale):
+    """Projected velocity (new arrays): every interior face f between c- and c+ gets
+    u_f - scale * beta_f * (p(c+) - p(c-)), scale = dt / h; wall faces are copied."""
+    u, v, w = _c(u).copy(), _c(v).copy(), _c(w).copy()
+    nx, ny, nz = _faces_dims(u, v, w)
+    bx, by, bz, p = _c(bx), _c(by), _c(bz), _c(p)
+    assert p.shape == (nz, ny, nx) and bx.shape == u.shape and by.shape == v.shape and bz.shape == w.shape
+    lib().og_correct_velocity(nx, ny, nz, _p(bx), _p(by), _p(bz), _p(p), float(scale), _p(u), _p(v), _p(w))
+    return u, v, w
+
+
+def project(bx, by, bz, u, v, w, dt, h, tol=1e-10, **solve_kw):
+    """The projection step in the paper's order: b = divergence(u*) with scale h/dt,
+    the pressure solve of L p = b - mean(b), then the velocity correction with scale
+    dt/h.  Returns dict(b, p, u, v, w, solve=<solve() result>)."""
+    b = divergence(u, v, w, h / dt)
+    res = solve(bx, by, bz, b, tol=tol, **solve_kw)
+    un, vn, wn = correct_velocity(bx, by, bz, res["p"], u, v, w, dt / h)
+    return dict(b=b, p=res["p"], u=un, v=vn, w=wn, solve=res)
 
 
 def last_timing():

@@ -433,6 +433,76 @@ int og_hierarchy_level(int nx, int ny, int nz, const double *bx, const double *b
 }
 
 /* ------------------------------------------------------------------------- */
+/* Projection step around the solve (Sec. 2.2)                                 */
+/* ------------------------------------------------------------------------- */
+/*
+ * The flow solver advances the velocity with Chorin's projection method on the
+ * staggered MAC mesh: each velocity component lives on the faces normal to it,
+ * the pressure in the cells, and every derivative is a second-order centred
+ * difference.  The source of the pressure equation (9) is the divergence of the
+ * non-projected velocity u* over the time step, S = div(u*) / dt; with the h^2
+ * of eq. (10) folded into the right-hand side,
+ *     b_c = h^2 S_c = (h / dt) * sum_d (u_d(upper face of c) - u_d(lower face of c)).
+ * The projected velocity is u = u* - dt (1/rho)_f grad p, on each interior face
+ * f between cells c- (lower index) and c+:
+ *     u_f = u*_f - (dt / h) * beta_f * (p(c+) - p(c-)),
+ * with beta_f the face coefficient of eq. (10); its discrete divergence is then
+ * (dt / h^2) (b - L p), zero once L p = b.  Wall faces keep their values (the
+ * pressure has homogeneous Neumann conditions there).
+ *
+ * Evaluation order (fixed, so another implementation can reproduce it):
+ *     b_c = scale * ((du + dv) + dw),  du = u(i+1) - u(i) etc.;
+ *     u_f = u_f - (scale * beta_f) * (p(c+) - p(c-)).
+ */
+static size_t fx_at(int nx, int ny, int i, int j, int k) { return ((size_t)k * ny + j) * (nx + 1) + i; }
+static size_t fy_at(int nx, int ny, int i, int j, int k) { return ((size_t)k * (ny + 1) + j) * nx + i; }
+static size_t fz_at(int nx, int ny, int i, int j, int k) { return ((size_t)k * ny + j) * nx + i; }
+static size_t c_at(int nx, int ny, int i, int j, int k) { return ((size_t)k * ny + j) * nx + i; }
+
+/* b = scale * (discrete divergence of (u, v, w) times h); scale = h / dt. */
+void og_divergence(int nx, int ny, int nz, const double *u, const double *v, const double *w,
+                   double scale, double *b)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                double du = u[fx_at(nx, ny, i + 1, j, k)] - u[fx_at(nx, ny, i, j, k)];
+                double dv = v[fy_at(nx, ny, i, j + 1, k)] - v[fy_at(nx, ny, i, j, k)];
+                double dw = w[fz_at(nx, ny, i, j, k + 1)] - w[fz_at(nx, ny, i, j, k)];
+                b[c_at(nx, ny, i, j, k)] = scale * ((du + dv) + dw);
+            }
+}
+
+/* u -= scale * beta * (pressure difference across the face), interior faces
+   only; scale = dt / h.  bx, by, bz in the face layout (walls not read). */
+void og_correct_velocity(int nx, int ny, int nz, const double *bx, const double *by, const double *bz,
+                         const double *p, double scale, double *u, double *v, double *w)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++) {
+            for (int i = 1; i < nx; i++) {
+                size_t f = fx_at(nx, ny, i, j, k);
+                double dp = p[c_at(nx, ny, i, j, k)] - p[c_at(nx, ny, i - 1, j, k)];
+                u[f] = u[f] - (scale * bx[f]) * dp;
+            }
+            if (j > 0)
+                for (int i = 0; i < nx; i++) {
+                    size_t f = fy_at(nx, ny, i, j, k);
+                    double dp = p[c_at(nx, ny, i, j, k)] - p[c_at(nx, ny, i, j - 1, k)];
+                    v[f] = v[f] - (scale * by[f]) * dp;
+                }
+            if (k > 0)
+                for (int i = 0; i < nx; i++) {
+                    size_t f = fz_at(nx, ny, i, j, k);
+                    double dp = p[c_at(nx, ny, i, j, k)] - p[c_at(nx, ny, i, j, k - 1)];
+                    w[f] = w[f] - (scale * bz[f]) * dp;
+                }
+        }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Driver                                                                      */
 /* ------------------------------------------------------------------------- */
 

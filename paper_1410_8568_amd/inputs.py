@@ -30,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "smoothed_heaviside", "cell_centres", "faces_from_alpha",
-    "divergence_rhs", "normal_rhs", "sphere_problem", "drop_splash_problem",
+    "divergence_rhs", "velocity_field", "normal_rhs", "sphere_problem", "drop_splash_problem",
     "config0", "config1", "config2", "batch_problems", "request_stream",
     "layered_problem", "constant_problem",
 ]
@@ -113,6 +113,32 @@ def divergence_rhs(n, rng: np.random.Generator) -> np.ndarray:
     uz[1:nz, :, :] = rng.standard_normal((nz - 1, ny, nx))
     b += uz[1:, :, :] - uz[:-1, :, :]
     return b
+
+
+def velocity_field(n, rng: np.random.Generator, walls: bool = False):
+    """Random face velocity (u on x-faces, v on y-faces, w on z-faces) for the
+    projection step.
+
+    Interior faces are i.i.d. N(0,1), drawn x-faces first, then y, then z, each in
+    C order over the interior faces only (the same draws as ``divergence_rhs``).
+    Wall faces are 0 (no penetration) or, with ``walls``, N(0,1) drawn after the
+    interior faces in the order x-lower, x-upper, y-lower, y-upper, z-lower,
+    z-upper."""
+    nx, ny, nz = n
+    u = np.zeros((nz, ny, nx + 1))
+    v = np.zeros((nz, ny + 1, nx))
+    w = np.zeros((nz + 1, ny, nx))
+    u[:, :, 1:nx] = rng.standard_normal((nz, ny, nx - 1))
+    v[:, 1:ny, :] = rng.standard_normal((nz, ny - 1, nx))
+    w[1:nz, :, :] = rng.standard_normal((nz - 1, ny, nx))
+    if walls:
+        u[:, :, 0] = rng.standard_normal((nz, ny))
+        u[:, :, nx] = rng.standard_normal((nz, ny))
+        v[:, 0, :] = rng.standard_normal((nz, nx))
+        v[:, ny, :] = rng.standard_normal((nz, nx))
+        w[0] = rng.standard_normal((ny, nx))
+        w[nz] = rng.standard_normal((ny, nx))
+    return u, v, w
 
 
 def _alpha_from_phi_planes(n, phi_plane, rho_l, rho_g, chunk=16):
