@@ -87,6 +87,69 @@ def cpu_baseline(P, n_coarsest, outer_needed, precision):
                        f"{wall:.1f} s of CPU wall time measured")
 
 
+# Algorithmic HBM bytes per cell of the two projection kernels (FP64): the
+# divergence reads the three face velocities and writes b; the correction reads
+# p and the three lower-face coefficients and reads and writes the velocities.
+PROJ_BYTES_PER_CELL = {"divergence": 32, "correct_velocity": 80}
+
+
+def projection_bench(S, n, steps, warmup, tol, dev):
+    """The projection step around the solve on the same coefficient field: MAC
+    divergence of a random face velocity (interior N(0,1), walls 0, seed 37),
+    the solve, and the velocity correction; dt = 1e-3, h = 1/n.  Each kernel is
+    timed over 10 back-to-back launches with HIP events on the stream it runs on;
+    the whole step (divergence + solve + correction, blocking) per step."""
+    import numpy as np
+    import torch
+    from paper_1410_8568_amd import inputs, mg
+    t = time.perf_counter()
+    u0, v0, w0 = (torch.from_numpy(a).to(dev) for a in inputs.velocity_field((n, n, n), np.random.default_rng(37)))
+    log(f"generated the {n}^3 velocity field in {time.perf_counter() - t:.1f} s")
+    u, v, w = u0.clone(), v0.clone(), w0.clone()
+    b = torch.empty((n, n, n), dtype=torch.float64, device=dev)
+    p = torch.zeros_like(b)
+    h, dt = 1.0 / n, 1e-3
+    N = n ** 3
+
+    def per_launch(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    step_ms, st = [], None
+    for i in range(warmup + steps):
+        u.copy_(u0)
+        v.copy_(v0)
+        w.copy_(w0)
+        p.zero_()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        st = S.project(u, v, w, dt, h, p=p, b=b, tol=tol)
+        e1.record()
+        torch.cuda.synchronize()
+        if i >= warmup:
+            step_ms.append(e0.elapsed_time(e1))
+    ms = {"divergence": per_launch(lambda: mg.divergence(u0, v0, w0, h / dt, b)),
+          "correct_velocity": per_launch(lambda: S.correct_velocity(p, u, v, w, dt / h))}
+    out = {"workload": f"projection step on the same field: random face velocity (seed 37), dt {dt:g}, h 1/{n}",
+           "ms_per_step": sorted(step_ms)[len(step_ms) // 2], "outer": st["outer"],
+           "final_rel_residual": st["rel_residual"]}
+    for k, v_ms in ms.items():
+        byt = PROJ_BYTES_PER_CELL[k] * N
+        gbps = byt / (v_ms * 1e-3) / 1e9
+        out[k] = {"avg_launch_ms": v_ms, "bytes_per_launch": byt, "achieved_gbps": gbps,
+                  "frac": gbps / HBM_PEAK_GBPS}
+    del u0, v0, w0, u, v, w
+    return out
+
+
 def kernel_source_sha():
     import hashlib
     h = hashlib.sha256()
@@ -335,6 +398,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--inner-m", type=int, default=0, help="FP32 V-cycles per outer iteration (0: library default)")
     ap.add_argument("--graph", type=int, default=1, help="replay each outer iteration as a HIP graph (1) or launch eagerly (0)")
+    ap.add_argument("--projection", type=int, default=1,
+                    help="also time the projection step around the solve (divergence, solve, correction)")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (counter scale)")
     ap.add_argument("--summarize", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
     ap.add_argument("--traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
@@ -422,6 +487,12 @@ def main():
         bytes64 = sum(prof64["kernel_bytes"].values())
         res["fp64_gbps_per_vcycle"] = bytes64 / cyc64 / 1e6 / (ms64 / cyc64)
         res["fp64_cell_updates_per_s"] = N * cyc64 / (ms64 * 1e-3)
+
+    if args.projection:
+        Sp, _ = build("fp32_refined")
+        res["projection_step"] = projection_bench(Sp, args.n, args.steps, args.warmup, args.tol, dev)
+        Sp.close()
+        log(f"projection step: {json.dumps(res['projection_step'])}")
 
     # dominant kernel of the timed (FP32-refined) step, from the profiled solve
     kms = prof32["kernel_ms"]

@@ -192,6 +192,66 @@ mg_status mg_copy_level(const mg_handle *h, int l, double *bx, double *by, doubl
                         void *stream);
 
 /* ------------------------------------------------------------------------- */
+/* Projection step around the solve                                           */
+/* ------------------------------------------------------------------------- */
+/*
+ * The pressure equation (9) comes from the flow solver's Chorin projection on
+ * the staggered MAC mesh (Sec. 2.2): velocity components on the faces normal to
+ * them (u on x-faces, v on y-faces, w on z-faces, the face layout above),
+ * pressure in the cells, centred differences.  Its source is S = div(u*) / dt,
+ * u* the velocity before projection, and the projected velocity is
+ * u = u* - dt (1/rho)_f grad p.  With cubic cells of side h and the h^2 of
+ * eq. (10) folded into b, the three calls below compute
+ *     b_c = (h/dt) * sum_d (u_d(upper face of c) - u_d(lower face of c))
+ *     u_f = u*_f - (dt/h) * beta_f * (p(c+) - p(c-))     (interior faces f)
+ * so that the discrete divergence of the projected field is (dt/h^2)(b - L p),
+ * zero to the solve's tolerance.  Wall faces of the velocity are used as given
+ * by the divergence (a nonzero wall flux gives b a nonzero mean, which the solve
+ * removes) and never changed by the correction.  Evaluation order is fixed and
+ * has no fused multiply-adds: b = scale*((du + dv) + dw) and
+ * u_f = u_f - (scale*beta_f)*(p(c+) - p(c-)).  FP64 throughout.
+ */
+
+/*
+ * b = scale * (net outflow of the face velocity out of each cell); scale = h/dt
+ * gives the right-hand side of the projection step.  g: cells per direction
+ * (each >= 0; an empty grid is a no-op).  u, v, w: device double face arrays
+ * (x-, y-, z-faces, walls included and read); b: device double [nz][ny][nx],
+ * written.  Asynchronous on `stream` (no synchronisation); the caller keeps the
+ * arrays alive until the stream has passed this call.
+ * Errors: MG_E_INVALID (NULL grid/array, negative dimension, non-finite scale,
+ * grid too large for one launch), MG_E_HIP (launch failure).
+ */
+mg_status mg_divergence(const mg_grid *g, const double *u, const double *v, const double *w, double scale,
+                        double *b, void *stream);
+
+/*
+ * u -= scale * beta * (p(c+) - p(c-)) on every interior face, beta the handle's
+ * level-0 face coefficients (the ones mg_setup received); scale = dt/h gives the
+ * velocity correction of the projection step.  Wall faces are not touched.
+ * p: device double cells; u, v, w: device double face arrays, in/out, of the
+ * handle's grid.  Asynchronous on `stream`.  Errors: MG_E_INVALID (NULL
+ * handle/array, non-finite scale), MG_E_HIP.
+ */
+mg_status mg_correct_velocity(const mg_handle *h, const double *p, double scale, double *u, double *v,
+                              double *w, void *stream);
+
+/*
+ * The whole projection step for the handle's coefficient field: b =
+ * mg_divergence(u, v, w, h/dt); mg_solve(b, p, tol); on MG_OK,
+ * mg_correct_velocity(p, dt/h, u, v, w).  dt: time step, hcell: cell size h
+ * (both finite and > 0).  b: device double cells, receives the right-hand side
+ * (workspace owned by the caller).  p: in/out as in mg_solve (initial guess in,
+ * mean-zero pressure out, in the h^2-scaled units of eq. 10).  u, v, w: in/out:
+ * u* in, projected velocity out.  st: as in mg_solve.  Blocking on return.
+ * If the solve does not succeed, its status is returned and u, v, w are left
+ * unchanged (b and p hold what the solve left).  Errors: those of mg_solve, and
+ * MG_E_INVALID for a bad dt or h.
+ */
+mg_status mg_project(mg_handle *h, double *u, double *v, double *w, double dt, double hcell, double *b,
+                     double *p, double tol, mg_stats *st, void *stream);
+
+/* ------------------------------------------------------------------------- */
 /* Continuous-batching solve server                                           */
 /* ------------------------------------------------------------------------- */
 

@@ -14,6 +14,8 @@
 
 #include <type_traits>
 
+#include "mg_device.h"
+
 namespace mgk {
 
 constexpr int BX = 64;   // threads along i (one wavefront)
@@ -453,15 +455,6 @@ __global__ void __launch_bounds__(512) k_coarse_solve(const double* __restrict__
 // the issuing thread, after the compiler's own wait.)
 __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
-// Map the dispatch order of workgroups onto tiles so that each XCD works on a
-// contiguous range of tiles: workgroup w is dispatched to XCD w % 8, and XCD x
-// receives logical tiles [start_x, start_x + count_x).  Neighbouring tiles then
-// share one L2, where their halo re-reads hit.
-__device__ __forceinline__ int xcd_tile(int w, int nwg) {
-    const int q = nwg >> 3, r = nwg & 7, x = w & 7, m = w >> 3;
-    return x * q + min(x, r) + m;
 }
 
 // Raw buffer access: a resource (base address, range, format word) in scalar

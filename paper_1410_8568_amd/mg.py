@@ -29,7 +29,8 @@ MG_K_COUNT = len(KERNEL_CLASSES)
 EXPORTS = [
     "mg_default_options", "mg_workspace_bytes", "mg_setup", "mg_solve", "mg_destroy",
     "mg_level_dims", "mg_level_tile", "mg_copy_level", "mg_server_create", "mg_batch_submit", "mg_poll",
-    "mg_server_destroy", "mg_status_string", "mg_last_error",
+    "mg_server_destroy", "mg_status_string", "mg_last_error", "mg_divergence", "mg_correct_velocity",
+    "mg_project",
 ]
 
 
@@ -108,6 +109,9 @@ def lib():
     L.mg_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Result)]
     L.mg_server_destroy.argtypes = [vp]
     L.mg_server_destroy.restype = None
+    L.mg_divergence.argtypes = [ctypes.POINTER(Grid), vp, vp, vp, d, vp, vp]
+    L.mg_correct_velocity.argtypes = [vp, vp, d, vp, vp, vp, vp]
+    L.mg_project.argtypes = [vp, vp, vp, vp, d, d, vp, vp, d, ctypes.POINTER(Stats), vp]
     L.mg_status_string.argtypes = [i]
     L.mg_status_string.restype = ctypes.c_char_p
     L.mg_last_error.argtypes = []
@@ -166,6 +170,31 @@ def _check_field(t, shape, name):
                          f"got {t.dtype} {tuple(t.shape)} on {t.device}")
 
 
+def _check_velocity(u, v, w, n):
+    nx, ny, nz = n
+    _check_field(u, (nz, ny, nx + 1), "u")
+    _check_field(v, (nz, ny + 1, nx), "v")
+    _check_field(w, (nz + 1, ny, nx), "w")
+
+
+def divergence(u, v, w, scale, b=None, stream=None):
+    """b = scale * (net face-velocity outflow of each cell) (scale = h/dt: the
+    right-hand side of the projection step).  Asynchronous on the stream."""
+    import torch
+    nz, ny, nxp = u.shape
+    n = (nxp - 1, ny, nz)
+    _check_velocity(u, v, w, n)
+    if b is None:
+        b = torch.empty((nz, ny, n[0]), dtype=torch.float64, device=u.device)
+    _check_field(b, (nz, ny, n[0]), "b")
+    g = Grid(*n)
+    rc = lib().mg_divergence(ctypes.byref(g), _ptr(u), _ptr(v), _ptr(w), ctypes.c_double(scale), _ptr(b),
+                             _stream(stream))
+    if rc != MG_OK:
+        raise MGError(rc, "mg_divergence")
+    return b
+
+
 class Solver:
     """One coefficient field: ``Solver(bx, by, bz)`` then ``solve(b, p)``.
 
@@ -207,6 +236,39 @@ class Solver:
             raise MGError(rc, "mg_solve")
         out = st.to_dict()
         out["rc"] = rc
+        return out
+
+    def correct_velocity(self, p, u, v, w, scale):
+        """In place: u -= scale * beta * (pressure difference) on every interior face
+        (scale = dt/h for the projection step).  Asynchronous on the solver's stream."""
+        nx, ny, nz = self.n
+        _check_field(p, (nz, ny, nx), "p")
+        _check_velocity(u, v, w, self.n)
+        rc = lib().mg_correct_velocity(self.h, _ptr(p), ctypes.c_double(scale), _ptr(u), _ptr(v), _ptr(w),
+                                       _stream(self.stream))
+        if rc != MG_OK:
+            raise MGError(rc, "mg_correct_velocity")
+
+    def project(self, u, v, w, dt, h, p=None, b=None, tol=1e-10, check=True):
+        """The projection step in place on (u, v, w): right-hand side into b, pressure
+        into p (both allocated if None), velocity corrected on success.  Returns the
+        stats dict with the tensors under "p" and "b"."""
+        import torch
+        nx, ny, nz = self.n
+        _check_velocity(u, v, w, self.n)
+        if p is None:
+            p = torch.zeros((nz, ny, nx), dtype=torch.float64, device=u.device)
+        if b is None:
+            b = torch.empty((nz, ny, nx), dtype=torch.float64, device=u.device)
+        _check_field(p, (nz, ny, nx), "p")
+        _check_field(b, (nz, ny, nx), "b")
+        st = Stats()
+        rc = lib().mg_project(self.h, _ptr(u), _ptr(v), _ptr(w), ctypes.c_double(dt), ctypes.c_double(h),
+                              _ptr(b), _ptr(p), ctypes.c_double(tol), ctypes.byref(st), _stream(self.stream))
+        if check and rc != MG_OK:
+            raise MGError(rc, "mg_project")
+        out = st.to_dict()
+        out.update(rc=rc, p=p, b=b)
         return out
 
     def levels(self):
