@@ -10,166 +10,143 @@
 // of the result is (dt / h^2) (b - L p).  Wall faces keep their values.
 //
 // Both kernels are pure streaming passes (about 32 and 80 bytes of HBM traffic
-// per cell, a handful of flops), bound by HBM bandwidth.  A workgroup owns a
-// 64 x 4 tile of columns and marches up a chunk of planes; each thread keeps the
-// values it shares with the next plane (the z-face velocity below the cell, the
-// pressure below it) in registers and loads the next plane's operands one step
-// ahead.  Arithmetic is evaluated in a fixed order without fused multiply-adds:
+// per cell, a handful of flops), bound by HBM bandwidth.  Each thread owns two
+// neighbouring cells of a row (16-byte loads and stores of every array whose
+// rows are aligned: cells, y- and z-faces; the x-face rows have nx + 1 entries
+// and are read as scalars), 512 threads per workgroup, workgroups in plain
+// dispatch order: for these passes, which re-read only a neighbouring row or
+// plane, that measured faster than column marching and than an XCD-grouped
+// order.  Odd nx or arrays that are not 16-byte aligned use one cell per thread.
+// Arithmetic is evaluated in a fixed order without fused multiply-adds:
 //     b = scale * ((du + dv) + dw),   u_f = u_f - (scale * beta_f) * (p(c+) - p(c-)).
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
-#include <climits>
 #include <cmath>
+#include <cstdint>
 #include <string>
 
 #include "mg_core.h"
-#include "mg_device.h"
 
 using mgrt::set_error;
 
 namespace {
 
-constexpr int PBX = 64, PBY = 4;   // columns per workgroup: one wavefront per row
-constexpr int P_TARGET_BLOCKS = 4096;
+constexpr int PT = 512;   // threads per workgroup
 
-struct PGrid {
-    int tiles_x, tiles_y, kc;
-    long nblocks;
+// First cell (i, j, k), index c, of this thread's unit of NC cells of a row.
+struct Unit {
+    uint32_t i, j, k;
+    size_t c;
 };
 
-// Tiles of columns and chunks of planes: about P_TARGET_BLOCKS workgroups, XCD
-// mapped by xcd_tile.
-PGrid pgrid(int nx, int ny, int nz) {
-    PGrid G;
-    G.tiles_x = (nx + PBX - 1) / PBX;
-    G.tiles_y = (ny + PBY - 1) / PBY;
-    const long tiles = (long)G.tiles_x * G.tiles_y;
-    long chunks = std::max(1L, std::min<long>(nz, (P_TARGET_BLOCKS + tiles - 1) / tiles));
-    G.kc = (int)((nz + chunks - 1) / chunks);
-    chunks = (nz + G.kc - 1) / G.kc;
-    G.nblocks = tiles * chunks;
-    return G;
+template <int NC>
+__device__ __forceinline__ bool unit_of(int nx, int ny, uint32_t units, Unit& q) {
+    const uint32_t t = blockIdx.x * PT + threadIdx.x;
+    if (t >= units) return false;
+    const uint32_t ux = (uint32_t)nx / NC;
+    const uint32_t r = t / ux;
+    q.i = (t - r * ux) * NC;
+    q.j = r % (uint32_t)ny;
+    q.k = r / (uint32_t)ny;
+    q.c = (size_t)r * nx + q.i;
+    return true;
 }
 
-struct Col {
-    int i, j, k0, k1;
-};
-
-__device__ __forceinline__ Col column(const PGrid& G, int nx, int ny, int nz) {
-    const int tile = mgk::xcd_tile(blockIdx.x, gridDim.x);
-    const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
-    Col c;
-    c.i = tx * PBX + (int)(threadIdx.x % PBX);
-    c.j = ty * PBY + (int)(threadIdx.x / PBX);
-    c.k0 = chunk * G.kc;
-    c.k1 = min(nz, c.k0 + G.kc);
-    return c;
-}
+__device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
+__device__ __forceinline__ void st2(double* p, double2 v) { *reinterpret_cast<double2*>(p) = v; }
 
 // b = scale * ((u(i+1) - u(i)) + (v(j+1) - v(j)) + (w(k+1) - w(k))) per cell.
-__global__ void __launch_bounds__(PBX* PBY)
+template <int NC>
+__global__ void __launch_bounds__(PT)
     k_divergence(const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
-                 double scale, double* __restrict__ b, int nx, int ny, int nz, PGrid G) {
+                 double scale, double* __restrict__ b, int nx, int ny, uint32_t units) {
 #pragma clang fp contract(off)
-    const Col q = column(G, nx, ny, nz);
-    if (q.i >= nx || q.j >= ny || q.k0 >= q.k1) return;
-    const size_t plane = (size_t)nx * ny, uplane = (size_t)(nx + 1) * ny, vplane = (size_t)nx * (ny + 1);
-    const double* up = u + (size_t)q.k0 * uplane + (size_t)q.j * (nx + 1) + q.i;
-    const double* vp = v + (size_t)q.k0 * vplane + (size_t)q.j * nx + q.i;
-    const double* wp = w + (size_t)q.k0 * plane + (size_t)q.j * nx + q.i;
-    double* bp = b + (size_t)q.k0 * plane + (size_t)q.j * nx + q.i;
-    double wlo = wp[0];
-    double u0 = up[0], u1 = up[1], v0 = vp[0], v1 = vp[nx], whi = wp[plane];
-    for (int k = q.k0; k < q.k1; k++) {
-        double nu0 = 0, nu1 = 0, nv0 = 0, nv1 = 0, nwhi = 0;
-        if (k + 1 < q.k1) {   // the next plane's loads stay in flight during this plane
-            up += uplane;
-            vp += vplane;
-            wp += plane;
-            nu0 = up[0];
-            nu1 = up[1];
-            nv0 = vp[0];
-            nv1 = vp[nx];
-            nwhi = wp[plane];
-        }
-        const double du = u1 - u0, dv = v1 - v0, dw = whi - wlo;
-        *bp = scale * ((du + dv) + dw);
-        bp += plane;
-        wlo = whi;
-        u0 = nu0;
-        u1 = nu1;
-        v0 = nv0;
-        v1 = nv1;
-        whi = nwhi;
+    Unit q;
+    if (!unit_of<NC>(nx, ny, units, q)) return;
+    const size_t plane = (size_t)nx * ny;
+    const size_t uo = ((size_t)q.k * ny + q.j) * (nx + 1) + q.i;   // x-face i of the row
+    const size_t vo = ((size_t)q.k * (ny + 1) + q.j) * nx + q.i;   // y-face j of the column
+    if constexpr (NC == 2) {
+        const double ua = u[uo], ub = u[uo + 1], uc = u[uo + 2];
+        const double2 v0 = ld2(v + vo), v1 = ld2(v + vo + nx), w0 = ld2(w + q.c), w1 = ld2(w + q.c + plane);
+        double2 o;
+        o.x = scale * (((ub - ua) + (v1.x - v0.x)) + (w1.x - w0.x));
+        o.y = scale * (((uc - ub) + (v1.y - v0.y)) + (w1.y - w0.y));
+        st2(b + q.c, o);
+    } else {
+        const double du = u[uo + 1] - u[uo], dv = v[vo + nx] - v[vo], dw = w[q.c + plane] - w[q.c];
+        b[q.c] = scale * ((du + dv) + dw);
     }
 }
 
-// Every cell corrects its three lower faces when they are interior:
-// x-face i (i > 0), y-face j (j > 0), z-face k (k > 0).  fx, fy, fz: the
-// solver's level-0 faces, lower face of each cell ([nz][ny][nx]).  Each interior
-// face has exactly one owner, so there are no write conflicts.
-__global__ void __launch_bounds__(PBX* PBY)
+// Every cell corrects its three lower faces when they are interior: x-face i
+// (i > 0), y-face j (j > 0), z-face k (k > 0).  fx, fy, fz: the solver's level-0
+// faces, lower face of each cell ([nz][ny][nx]).  Each interior face has exactly
+// one owner, so there are no write conflicts.
+template <int NC>
+__global__ void __launch_bounds__(PT)
     k_correct(const double* __restrict__ fx, const double* __restrict__ fy, const double* __restrict__ fz,
               const double* __restrict__ p, double scale, double* __restrict__ u, double* __restrict__ v,
-              double* __restrict__ w, int nx, int ny, int nz, PGrid G) {
+              double* __restrict__ w, int nx, int ny, uint32_t units) {
 #pragma clang fp contract(off)
-    const Col q = column(G, nx, ny, nz);
-    if (q.i >= nx || q.j >= ny || q.k0 >= q.k1) return;
-    const size_t plane = (size_t)nx * ny, uplane = (size_t)(nx + 1) * ny, vplane = (size_t)nx * (ny + 1);
-    const bool xin = q.i > 0, yin = q.j > 0;
-    // neighbour offsets clamped to the cell itself on the lower walls (no store there)
-    const size_t xm = xin ? 1 : 0, ym = yin ? (size_t)nx : 0;
-    size_t c = (size_t)q.k0 * plane + (size_t)q.j * nx + q.i;
-    size_t fu = (size_t)q.k0 * uplane + (size_t)q.j * (nx + 1) + q.i;
-    size_t fv = (size_t)q.k0 * vplane + (size_t)q.j * nx + q.i;
-    double pbelow = q.k0 > 0 ? p[c - plane] : 0.0;
-    double pc = p[c], pw = p[c - xm], ps = p[c - ym];
-    double bxc = fx[c], byc = fy[c], bzc = fz[c];
-    double uc = u[fu], vc = v[fv], wc = w[c];
-    for (int k = q.k0; k < q.k1; k++) {
-        const size_t cn = c + plane, fun = fu + uplane, fvn = fv + vplane;
-        double npc = 0, npw = 0, nps = 0, nbx = 0, nby = 0, nbz = 0, nu = 0, nv = 0, nw = 0;
-        if (k + 1 < q.k1) {   // the next plane's loads stay in flight during this plane
-            npc = p[cn];
-            npw = p[cn - xm];
-            nps = p[cn - ym];
-            nbx = fx[cn];
-            nby = fy[cn];
-            nbz = fz[cn];
-            nu = u[fun];
-            nv = v[fvn];
-            nw = w[cn];
+    Unit q;
+    if (!unit_of<NC>(nx, ny, units, q)) return;
+    const size_t plane = (size_t)nx * ny, c = q.c;
+    const size_t fu = ((size_t)q.k * ny + q.j) * (nx + 1) + q.i;
+    const size_t fv = ((size_t)q.k * (ny + 1) + q.j) * nx + q.i;
+    if constexpr (NC == 2) {
+        const double2 pc = ld2(p + c), bx = ld2(fx + c);
+        const double pw = p[q.i > 0 ? c - 1 : c];
+        const double u0 = u[fu], u1 = u[fu + 1];
+        if (q.i > 0) u[fu] = u0 - (scale * bx.x) * (pc.x - pw);
+        u[fu + 1] = u1 - (scale * bx.y) * (pc.y - pc.x);   // face i + 1 is always interior
+        if (q.j > 0) {
+            const double2 ps = ld2(p + c - nx), by = ld2(fy + c), vv = ld2(v + fv);
+            double2 o;
+            o.x = vv.x - (scale * by.x) * (pc.x - ps.x);
+            o.y = vv.y - (scale * by.y) * (pc.y - ps.y);
+            st2(v + fv, o);
         }
-        if (xin) u[fu] = uc - (scale * bxc) * (pc - pw);
-        if (yin) v[fv] = vc - (scale * byc) * (pc - ps);
-        if (k > 0) w[c] = wc - (scale * bzc) * (pc - pbelow);
-        pbelow = pc;
-        c = cn;
-        fu = fun;
-        fv = fvn;
-        pc = npc;
-        pw = npw;
-        ps = nps;
-        bxc = nbx;
-        byc = nby;
-        bzc = nbz;
-        uc = nu;
-        vc = nv;
-        wc = nw;
+        if (q.k > 0) {
+            const double2 pb = ld2(p + c - plane), bz = ld2(fz + c), ww = ld2(w + c);
+            double2 o;
+            o.x = ww.x - (scale * bz.x) * (pc.x - pb.x);
+            o.y = ww.y - (scale * bz.y) * (pc.y - pb.y);
+            st2(w + c, o);
+        }
+    } else {
+        const double pc = p[c];
+        if (q.i > 0) u[fu] = u[fu] - (scale * fx[c]) * (pc - p[c - 1]);
+        if (q.j > 0) v[fv] = v[fv] - (scale * fy[c]) * (pc - p[c - nx]);
+        if (q.k > 0) w[c] = w[c] - (scale * fz[c]) * (pc - p[c - plane]);
     }
 }
 
-bool grid_fits(const PGrid& G) { return G.nblocks > 0 && G.nblocks <= INT_MAX; }
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+// Units of work and workgroups for a grid; false if the grid is too large for
+// the 32-bit unit index (about 4e9 cells, far beyond one GPU's memory).
+bool launch_shape(const mg_grid& g, int nc, uint32_t* units, unsigned* blocks) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz / nc;
+    if (n > (size_t)UINT32_MAX - PT) {
+        set_error("grid too large for one launch");
+        return false;
+    }
+    *units = (uint32_t)n;
+    *blocks = (unsigned)((n + PT - 1) / PT);
+    return true;
+}
 
 mg_status launch_divergence(const mg_grid& g, const double* u, const double* v, const double* w, double scale,
                             double* b, hipStream_t s) {
-    const PGrid G = pgrid(g.nx, g.ny, g.nz);
-    if (!grid_fits(G)) {
-        set_error("grid too large for one launch");
-        return MG_E_INVALID;
-    }
-    k_divergence<<<dim3((unsigned)G.nblocks), PBX * PBY, 0, s>>>(u, v, w, scale, b, g.nx, g.ny, g.nz, G);
+    const bool pair = (g.nx % 2) == 0 && aligned16(v) && aligned16(w) && aligned16(b);
+    uint32_t units;
+    unsigned blocks;
+    if (!launch_shape(g, pair ? 2 : 1, &units, &blocks)) return MG_E_INVALID;
+    if (pair)
+        k_divergence<2><<<blocks, PT, 0, s>>>(u, v, w, scale, b, g.nx, g.ny, units);
+    else
+        k_divergence<1><<<blocks, PT, 0, s>>>(u, v, w, scale, b, g.nx, g.ny, units);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error(std::string("k_divergence launch: ") + hipGetErrorString(e));
@@ -181,13 +158,14 @@ mg_status launch_divergence(const mg_grid& g, const double* u, const double* v, 
 mg_status launch_correct(const mg_handle* h, const double* p, double scale, double* u, double* v, double* w,
                          hipStream_t s) {
     const mg_grid& g = h->g;
-    const PGrid G = pgrid(g.nx, g.ny, g.nz);
-    if (!grid_fits(G)) {
-        set_error("grid too large for one launch");
-        return MG_E_INVALID;
-    }
-    k_correct<<<dim3((unsigned)G.nblocks), PBX * PBY, 0, s>>>(h->bx[0], h->by[0], h->bz[0], p, scale, u, v, w, g.nx,
-                                                               g.ny, g.nz, G);
+    const bool pair = (g.nx % 2) == 0 && aligned16(p) && aligned16(v) && aligned16(w);   // faces: 256-aligned
+    uint32_t units;
+    unsigned blocks;
+    if (!launch_shape(g, pair ? 2 : 1, &units, &blocks)) return MG_E_INVALID;
+    if (pair)
+        k_correct<2><<<blocks, PT, 0, s>>>(h->bx[0], h->by[0], h->bz[0], p, scale, u, v, w, g.nx, g.ny, units);
+    else
+        k_correct<1><<<blocks, PT, 0, s>>>(h->bx[0], h->by[0], h->bz[0], p, scale, u, v, w, g.nx, g.ny, units);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error(std::string("k_correct launch: ") + hipGetErrorString(e));

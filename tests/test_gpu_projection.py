@@ -42,8 +42,9 @@ def velocity(n, seed, walls):
     return inputs.velocity_field(n, np.random.default_rng(seed), walls=walls)
 
 
-# tiles are 64 x 4 columns; chunks of planes: grids below span several tiles and
-# chunks with ragged edges, and the degenerate one-cell and one-plane cases
+# one thread per two cells of a row (odd nx: per cell), 512 per workgroup: grids
+# below span several workgroups with ragged ends, odd and even nx, and the
+# degenerate one-cell and one-plane cases
 GRIDS = [(1, 1, 1), (5, 7, 3), (70, 9, 13), (128, 8, 64), (130, 6, 2), (64, 4, 1), (3, 200, 5)]
 
 
@@ -89,6 +90,35 @@ def test_correction_bit_exact(n):
     gu, gv, gw, gp = dev(u, v, w, p)
     S.correct_velocity(gp, gu, gv, gw, 0.61)
     ou, ov, ow = oracle.correct_velocity(bx, by, bz, p, u, v, w, 0.61)
+    hu, hv, hw = host(gu, gv, gw)
+    assert np.array_equal(hu, ou) and np.array_equal(hv, ov) and np.array_equal(hw, ow)
+    S.close()
+
+
+def unaligned(a):
+    """Device copy of `a` that starts 8 bytes past a 16-byte boundary (the kernels
+    then take their one-cell-per-thread path)."""
+    import torch
+    buf = torch.empty(a.size + 1, dtype=torch.float64, device="cuda")
+    t = buf[1:].view(a.shape)
+    t.copy_(torch.from_numpy(np.ascontiguousarray(a)))
+    assert t.data_ptr() % 16 == 8 and t.is_contiguous()
+    return t
+
+
+def test_unaligned_arrays_take_the_scalar_path_bit_exactly():
+    from paper_1410_8568_amd import mg
+    n = (72, 12, 16)
+    rng = np.random.default_rng(38)
+    bx, by, bz = pins.random_faces(n, rng, contrast=1000.0)
+    p = rng.standard_normal((16, 12, 72))
+    u, v, w = velocity(n, 39, walls=True)
+    b, = host(mg.divergence(unaligned(u), unaligned(v), unaligned(w), 1.7, unaligned(np.zeros((16, 12, 72)))))
+    assert np.array_equal(b, oracle.divergence(u, v, w, 1.7))
+    S = mg.Solver(*dev(bx, by, bz))
+    gu, gv, gw, gp = unaligned(u), unaligned(v), unaligned(w), unaligned(p)
+    S.correct_velocity(gp, gu, gv, gw, 0.3)
+    ou, ov, ow = oracle.correct_velocity(bx, by, bz, p, u, v, w, 0.3)
     hu, hv, hw = host(gu, gv, gw)
     assert np.array_equal(hu, ou) and np.array_equal(hv, ov) and np.array_equal(hw, ow)
     S.close()
