@@ -42,7 +42,7 @@ _I = ctypes.POINTER(ctypes.c_int)
 class OgOpts(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("n_coarsest", ctypes.c_int),
                 ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int),
-                ("inner_m", ctypes.c_int), ("tol", ctypes.c_double)]
+                ("inner_m", ctypes.c_int), ("tol", ctypes.c_double), ("krylov", ctypes.c_int)]
 
 
 def lib():
@@ -192,14 +192,20 @@ def hierarchy_level(bx, by, bz, n_coarsest, level):
 STATUS = {0: "converged", 1: "not_converged", 2: "diverged", -1: "invalid"}
 
 
+KRYLOV = {"none": 0, "fcg": 1, "cg": 2}
+
+
 def solve(bx, by, bz, b, p0=None, nu1=2, nu2=2, n_coarsest=4, max_cycles=100, tol=1e-10,
-          precision="fp64", inner_m=3):
-    """Run the oracle solve.  Returns dict(p, history, cycles, status, gamma, mean_b)."""
+          precision="fp64", inner_m=3, krylov="none"):
+    """Run the oracle solve.  Returns dict(p, history, cycles, status, gamma, mean_b).
+
+    krylov: "none" (V-cycle iteration), "fcg" (flexible CG preconditioned by one
+    V-cycle per iteration, FP64) or "cg" (unpreconditioned CG, for the tests)."""
     b = _c(b)
     nx, ny, nz = dims_of(b)
     p = np.zeros_like(b) if p0 is None else _c(p0).copy()
     o = OgOpts(nu1, nu2, n_coarsest, max_cycles, {"fp64": 0, "fp32_refined": 1}[precision],
-               inner_m, tol)
+               inner_m, tol, KRYLOV[krylov])
     hist = np.zeros(max_cycles + 1)
     ncyc = ctypes.c_int(0)
     mean_b = ctypes.c_double(0)

@@ -513,6 +513,8 @@ typedef struct {
     int precision;   /* 0: FP64 multigrid, 1: FP32 V-cycles inside FP64 refinement */
     int inner_m;     /* FP32 V-cycles per outer iteration */
     double tol;      /* relative residual ||b_bar - L p|| / ||b_bar|| */
+    int krylov;      /* FP64 only: 0 V-cycle iteration, 1 flexible CG preconditioned by one
+                        V-cycle, 2 unpreconditioned CG (for the tests) */
 } og_opts;
 
 /*
@@ -535,6 +537,72 @@ static double wall(void)
 #else
     return 0.0;
 #endif
+}
+
+static double dot_d(const double *a, const double *b, size_t n)
+{
+    double s = 0.0;
+    for (size_t t = 0; t < n; t++) s += a[t] * b[t];
+    return s;
+}
+
+/*
+ * Krylov acceleration of the multigrid solve (FP64): flexible conjugate
+ * gradients, FCG(1) of Notay (SIAM J. Sci. Comput. 22, 2000), on A = -L, which
+ * is symmetric positive definite on mean-free vectors.  The preconditioner is
+ * one V-cycle from a zero guess; since the paper's restriction and
+ * prolongation are not transposes of each other the cycle is not a symmetric
+ * operator, which the flexible form tolerates: each new direction is made
+ * A-orthogonal to the previous one explicitly.  Written with L itself (signs
+ * folded in; z = V(r) approximates L^-1 r):
+ *     z = V(r);  beta = -(z . q) / (s . q)  (0 on the first iteration);
+ *     s = z + beta s;  q = L s;  alpha = (r . z) / (s . q);
+ *     p += alpha s;  r = b_bar - L p   (the true residual, every iteration).
+ * krylov = 2 replaces the preconditioner by the identity on A (z = -r), which
+ * is textbook CG.  p is made mean-zero once, at the end.  Returns the status
+ * as og_solve and fills hist / *ncycles with one entry per iteration.
+ */
+static int krylov_solve(hier_t *H, const double *bbar, double nb, double *p, const og_opts *o, double *hist,
+                        int *ncycles, double rho0)
+{
+    level_d *F = &H->d[0];
+    size_t n = ncell(F->nx, F->ny, F->nz);
+    double *r = (double *)malloc(n * sizeof(double));
+    double *z = (double *)calloc(n, sizeof(double));
+    double *sd = (double *)calloc(n, sizeof(double));
+    double *q = (double *)calloc(n, sizeof(double));
+    double sq = 0.0, rho = rho0;
+    int status = rho0 <= o->tol ? 0 : 1, it = 0;
+    residual_d(F, p, bbar, r);
+    while (status == 1 && it < o->max_cycles) {
+        if (o->krylov == 1) {
+            memset(z, 0, n * sizeof(double));
+            F->e = z;
+            F->rhs = r;
+            vcycle_d(H->d, H->nlev, 0, &H->C, o->nu1, o->nu2);
+        } else {
+            for (size_t t = 0; t < n; t++) z[t] = -r[t];
+        }
+        double zq = dot_d(z, q, n), rz = dot_d(r, z, n);
+        double beta = sq == 0.0 ? 0.0 : -zq / sq;
+        for (size_t t = 0; t < n; t++) sd[t] = z[t] + beta * sd[t];
+        apply_d(F, sd, q);
+        sq = dot_d(sd, q, n);
+        double alpha = rz / sq;
+        for (size_t t = 0; t < n; t++) p[t] += alpha * sd[t];
+        residual_d(F, p, bbar, r);
+        rho = sqrt(sumsq_d(r, n)) / nb;
+        hist[++it] = rho;
+        if (!(rho == rho) || rho > 1e6 * rho0) status = 2;
+        else if (rho <= o->tol) status = 0;
+    }
+    double mp = sum_d(p, n) / (double)n;
+    for (size_t t = 0; t < n; t++) p[t] -= mp;
+    F->e = 0;
+    F->rhs = 0;
+    free(r); free(z); free(sd); free(q);
+    *ncycles = it;
+    return status;
 }
 
 int og_solve(int nx, int ny, int nz, const double *bx, const double *by, const double *bz,
@@ -579,7 +647,17 @@ int og_solve(int nx, int ny, int nz, const double *bx, const double *by, const d
     hist[0] = rho0;
     if (rho0 <= o->tol) status = 0;
 
-    if (o->precision == 0) {
+    if (o->precision == 0 && o->krylov != 0) {
+        if (o->krylov != 1 && o->krylov != 2) {
+            free(bbar);
+            F->e = 0; F->rhs = 0;
+            hier_free(&H);
+            return -1;
+        }
+        F->e = 0;
+        status = krylov_solve(&H, bbar, nb, p, o, hist, &cyc, rho0);
+        if (cyc > 0) rho = hist[cyc];
+    } else if (o->precision == 0) {
         while (status == 1 && cyc < o->max_cycles) {
             vcycle_d(H.d, H.nlev, 0, &H.C, o->nu1, o->nu2);
             double mp = sum_d(p, n) / (double)n;
