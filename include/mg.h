@@ -91,7 +91,17 @@ typedef struct {
                         iteration of a solve and replay it for the others (fewer host launches;
                         identical results).  Ignored when profile is set.  The server always
                         uses graphs. */
+    int krylov;      /* MG_KRYLOV_NONE (default): iterate V-cycles.  MG_KRYLOV_FCG (FP64 precision
+                        only): flexible conjugate gradients on -L (Notay's FCG(1)) with one V-cycle
+                        from zero as the preconditioner of every iteration; each new direction is
+                        made -L-orthogonal to the previous one explicitly, which the V-cycle needs
+                        since its restriction and prolongation are not transposes.  The residual
+                        b_bar - L p is recomputed every iteration, so history and tolerance mean
+                        the same as for the V-cycle iteration; stats.cycles counts iterations (one
+                        V-cycle each).  Needs 32 more bytes of workspace per cell. */
 } mg_options;
+
+enum { MG_KRYLOV_NONE = 0, MG_KRYLOV_FCG = 1 };
 
 /* Fused sweep variants: variant v uses tile (v-1)/2 of the list 64x8, 128x4,
    128x8, 64x16 (one sweep per pass), 64x4, 64x8, 128x8, 64x16 (two sweeps per
@@ -109,7 +119,8 @@ enum {
     MG_K_REFINE = 5,      /* FP64 refinement residual and update (refined mode) */
     MG_K_OTHER = 6,       /* projections, reductions, fills */
     MG_K_SMOOTH_FINE = 7, /* the smoother on the finest level only (subset of MG_K_SMOOTH) */
-    MG_K_COUNT = 8
+    MG_K_KRYLOV = 8,      /* Krylov vector passes: dot products, direction, update, residual */
+    MG_K_COUNT = 9
 };
 
 typedef struct {

@@ -34,6 +34,7 @@ struct Layout {
     size_t fbx[MG_MAX_LEVELS], fby[MG_MAX_LEVELS], fbz[MG_MAX_LEVELS], fa[MG_MAX_LEVELS];
     size_t fe[MG_MAX_LEVELS], frhs[MG_MAX_LEVELS];                // FP32 levels (refined mode)
     size_t bbar = 0, binv = 0, scal = 0, part = 0, flag = 0;
+    size_t kr = 0, kz = 0, ks = 0, kq = 0;                         // Krylov vectors (level 0, FP64)
     int ncoarse = 0;
     int max_blocks = 0;
     size_t total = 0;
@@ -63,6 +64,7 @@ struct mg_handle {
     double* scal = nullptr;
     double* part = nullptr;
     int* flag = nullptr;
+    double *kr = nullptr, *kz = nullptr, *ks = nullptr, *kq = nullptr;   // Krylov: r, z, s, q
     hipStream_t stream = nullptr;
     double* host = nullptr;  // pinned host copy of device scalars
     int tile[MG_MAX_LEVELS];   // smoother variant per level

@@ -93,8 +93,12 @@ mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
     }
     if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 16 || o->nu2 > 16 || o->n_coarsest < 1 || o->inner_m < 1 ||
         o->inner_m > 16 || o->max_cycles < 1 || o->max_cycles > MG_MAX_HISTORY - 1 || o->tile < -1 ||
-        o->tile > MG_NUM_TILES) {
+        o->tile > MG_NUM_TILES || (o->krylov != MG_KRYLOV_NONE && o->krylov != MG_KRYLOV_FCG)) {
         set_error("option out of range");
+        return MG_E_INVALID;
+    }
+    if (o->krylov == MG_KRYLOV_FCG && o->precision != MG_FP64) {
+        set_error("the Krylov solve runs in FP64 precision only");
         return MG_E_INVALID;
     }
     *L = Layout();
@@ -150,6 +154,12 @@ mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
         }
     }
     L->bbar = take(L->d[0].ncell() * 8);
+    if (o->krylov == MG_KRYLOV_FCG) {
+        L->kr = take(L->d[0].ncell() * 8);
+        L->kz = take(L->d[0].ncell() * 8);
+        L->ks = take(L->d[0].ncell() * 8);
+        L->kq = take(L->d[0].ncell() * 8);
+    }
     L->binv = take((size_t)L->ncoarse * L->ncoarse * 8);
     L->scal = take(64 * 8);
     int mb = 0;
@@ -250,6 +260,11 @@ static void bind(mg_handle* h) {
     h->scal = (double*)(w + L.scal);
     h->part = (double*)(w + L.part);
     h->flag = (int*)(w + L.flag);
+    const bool kry = h->o.krylov == MG_KRYLOV_FCG;
+    h->kr = kry ? (double*)(w + L.kr) : nullptr;
+    h->kz = kry ? (double*)(w + L.kz) : nullptr;
+    h->ks = kry ? (double*)(w + L.ks) : nullptr;
+    h->kq = kry ? (double*)(w + L.kq) : nullptr;
 }
 
 mg_status setup_launch(mg_handle* h, const double* bx, const double* by, const double* bz) {
@@ -691,14 +706,14 @@ static void build_hier(mg_handle* h, double* p, Hier<double>& H64, Hier<float>& 
 // kernel when nx is even.  Returns the number of partial-sum blocks.
 template <int MODE>
 static int launch_resid(hipStream_t s, const Lvl<double>& L, const double* p, const double* b,
-                        const double* inv_s, float* r32, double* part) {
+                        const double* inv_s, float* r32, double* part, double* r64 = nullptr) {
     int nb = 0;
     if ((L.nx & 1) == 0) {
         const ColGrid G = zgrid(L.nx / 2, L.ny, L.nz, false, &nb);
-        k_resid_cells<double, 2, MODE><<<nb, CBX * CBY, 0, s>>>(L, p, b, G, inv_s, r32, part);
+        k_resid_cells<double, 2, MODE><<<nb, CBX * CBY, 0, s>>>(L, p, b, G, inv_s, r32, part, r64);
     } else {
         const ColGrid G = zgrid(L.nx, L.ny, L.nz, false, &nb);
-        k_resid_col<double, MODE><<<nb, CBX * CBY, 0, s>>>(L, p, b, G, inv_s, r32, part);
+        k_resid_col<double, MODE><<<nb, CBX * CBY, 0, s>>>(L, p, b, G, inv_s, r32, part, r64);
     }
     return nb;
 }
@@ -736,6 +751,16 @@ mg_status solve_begin_launch(SolveState& S) {
         k_refine_scale<<<1, 64, 0, s>>>(h->scal + 3, N, h->scal + 8);
         Prof pf(h, MG_K_REFINE, resid_bytes + 4.0 * N);
         nbz = launch_resid<1>(s, L64, S.p, h->bbar, h->scal + 9, h->frhs[0], h->part);
+    } else if (h->o.krylov == MG_KRYLOV_FCG) {
+        {
+            Prof pf(h, MG_K_KRYLOV, resid_bytes + 8.0 * N);
+            nbz = launch_resid<2>(s, L64, S.p, h->bbar, nullptr, nullptr, h->part, h->kr);
+        }
+        // no previous direction: s = q = 0 and s.q = 0 (so the first beta is 0)
+        Prof pf(h, MG_K_KRYLOV, 16.0 * N);
+        k_fill<double><<<lin_grid(d0.ncell()), 256, 0, s>>>(h->ks, d0.ncell(), 0.0);
+        k_fill<double><<<lin_grid(d0.ncell()), 256, 0, s>>>(h->kq, d0.ncell(), 0.0);
+        k_fill<double><<<1, 64, 0, s>>>(h->scal + 12, 1, 0.0);
     } else {
         Prof pf(h, MG_K_NORM, resid_bytes);
         nbz = launch_resid<0>(s, L64, S.p, h->bbar, nullptr, nullptr, h->part);
@@ -792,7 +817,37 @@ static mg_status launch_iteration_kernels(SolveState& S) {
     Hier<float> H32;
     build_hier(h, S.p, H64, H32);
     int nbz = 0;
-    if (!f32) {
+    if (h->o.krylov == MG_KRYLOV_FCG) {
+        // z = V(r) from zero, then the direction, the update and the new residual
+        Hier<double> HK = H64;
+        HK.e[0] = h->kz;
+        HK.rhs[0] = h->kr;
+        vcycle(h, HK, 0, nullptr, true);
+        {
+            Prof pf(h, MG_K_KRYLOV, 24.0 * N);
+            k_fcg_dots<<<g0, blk, 0, s>>>(h->kz, h->kq, h->kr, d0.nx, d0.ny, d0.nz, h->part);
+        }
+        finish(h, (int)(g0.x * g0.y * g0.z), 10);
+        k_fcg_beta<<<1, 64, 0, s>>>(h->scal);
+        {
+            Prof pf(h, MG_K_KRYLOV, (3.0 * N + d0.nfaces()) * 8.0);
+            int nbd = 0;
+            if ((d0.nx & 1) == 0) {
+                const ColGrid G = zgrid(d0.nx / 2, d0.ny, d0.nz, false, &nbd);
+                k_fcg_direction<2><<<nbd, CBX * CBY, 0, s>>>(L64, h->kz, h->ks, h->scal, G, h->kq, h->part);
+            } else {
+                const ColGrid G = zgrid(d0.nx, d0.ny, d0.nz, false, &nbd);
+                k_fcg_direction<1><<<nbd, CBX * CBY, 0, s>>>(L64, h->kz, h->ks, h->scal, G, h->kq, h->part);
+            }
+            finish(h, nbd, 12);
+        }
+        {
+            Prof pf(h, MG_K_KRYLOV, 40.0 * N);
+            k_fcg_update<<<lin_grid(d0.ncell()), 256, 0, s>>>(h->kz, h->ks, S.p, h->scal, d0.ncell());
+        }
+        Prof pf(h, MG_K_KRYLOV, resid_bytes + 8.0 * N);
+        nbz = launch_resid<2>(s, L64, S.p, h->bbar, nullptr, nullptr, h->part, h->kr);
+    } else if (!f32) {
         const double* shift = h->scal + 5;
         if (!fused_first_sweep(h)) {
             Prof pf(h, MG_K_OTHER, 16.0 * N);
@@ -959,6 +1014,7 @@ mg_status mg_default_options(mg_options* o) {
     o->profile = 0;
     o->tile = 0;
     o->graph = 0;
+    o->krylov = MG_KRYLOV_NONE;
     return MG_OK;
 }
 

@@ -897,11 +897,13 @@ __device__ __forceinline__ Plane1<T> load_plane1(const Lvl<T>& L, const T* __res
 }
 
 // Residual r = b - L p along each column; MODE 0: partial sums of r^2 and p;
-// MODE 1 (FP64 refinement): also writes r32 = float(r * scal_inv_s[0]).
+// MODE 1 (FP64 refinement): also writes r32 = float(r * scal_inv_s[0]);
+// MODE 2 (Krylov solve): also writes r64 = r.
 template <class T, int MODE>
 __global__ void __launch_bounds__(CBX* CBY) k_resid_col(Lvl<T> L, const T* __restrict__ p, const T* __restrict__ b,
                                                        ColGrid G, const double* __restrict__ scal_inv_s,
-                                                       float* __restrict__ r32, double* __restrict__ part) {
+                                                       float* __restrict__ r32, double* __restrict__ part,
+                                                       T* __restrict__ r64) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
     const int i = tx * CBX + (int)(threadIdx.x % CBX), j = ty * CBY + (int)(threadIdx.x / CBX);
@@ -924,6 +926,7 @@ __global__ void __launch_bounds__(CBX* CBY) k_resid_col(Lvl<T> L, const T* __res
             const T d = stencil_diag(cur.wx0, cur.wx1, cur.wy0, cur.wy1, wz0, cur.wz1);
             const T r = resid_val(cur.b, s, d, cur.p);
             if (MODE == 1) r32[(size_t)k * plane + col] = (float)((double)r * inv_s);
+            if (MODE == 2) r64[(size_t)k * plane + col] = r;
             a += (double)r * (double)r;
             q += (double)cur.p;
             pbelow = cur.p;
@@ -957,7 +960,7 @@ __global__ void __launch_bounds__(CBX* CBY) k_resid_col(Lvl<T> L, const T* __res
 // Latency is hidden by occupancy (few registers per thread) rather than by
 // loading planes further ahead, which measured no faster here.
 
-// NC consecutive values as one vector load (NC = 2 or 4; 16 bytes at most).
+// NC consecutive values as one vector load (NC = 2 or 4; 16 bytes at most; NC = 1 a scalar).
 template <class T, int NC>
 struct VecN;
 template <>
@@ -975,15 +978,19 @@ struct VecN<double, 2> {
 
 template <class T, int NC>
 __device__ __forceinline__ void load_n(const T* src, T (&d)[NC]) {
-    const typename VecN<T, NC>::type v = *reinterpret_cast<const typename VecN<T, NC>::type*>(src);
-    if constexpr (NC == 2) {
-        d[0] = v.x;
-        d[1] = v.y;
+    if constexpr (NC == 1) {
+        d[0] = *src;
     } else {
-        d[0] = v.x;
-        d[1] = v.y;
-        d[2] = v.z;
-        d[3] = v.w;
+        const typename VecN<T, NC>::type v = *reinterpret_cast<const typename VecN<T, NC>::type*>(src);
+        if constexpr (NC == 2) {
+            d[0] = v.x;
+            d[1] = v.y;
+        } else {
+            d[0] = v.x;
+            d[1] = v.y;
+            d[2] = v.z;
+            d[3] = v.w;
+        }
     }
 }
 
@@ -1061,7 +1068,8 @@ template <class T, int NC, int MODE>
 __global__ void __launch_bounds__(CBX* CBY) k_resid_cells(Lvl<T> L, const T* __restrict__ p,
                                                          const T* __restrict__ b, ColGrid G,
                                                          const double* __restrict__ scal_inv_s,
-                                                         float* __restrict__ r32, double* __restrict__ part) {
+                                                         float* __restrict__ r32, double* __restrict__ part,
+                                                         T* __restrict__ r64) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
     const int I = tx * CBX + (int)(threadIdx.x % CBX), j = ty * CBY + (int)(threadIdx.x / CBX);
@@ -1087,6 +1095,10 @@ __global__ void __launch_bounds__(CBX* CBY) k_resid_cells(Lvl<T> L, const T* __r
                     *reinterpret_cast<float2*>(r32 + (size_t)k * plane + o.c) = make_float2(w[0], w[1]);
                 else
                     *reinterpret_cast<float4*>(r32 + (size_t)k * plane + o.c) = make_float4(w[0], w[1], w[2], w[3]);
+            }
+            if (MODE == 2) {
+#pragma unroll
+                for (int e = 0; e < NC; e++) r64[(size_t)k * plane + o.c + e] = r[e];
             }
 #pragma unroll
             for (int e = 0; e < NC; e++) {
@@ -1292,6 +1304,123 @@ __global__ void k_refine_update(double* __restrict__ p, const float* __restrict_
     const double s = scal_s[0];
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
         p[t] = (p[t] - c) + s * (double)e[t];
+}
+
+// ---------------------------------------------------------------- Krylov acceleration
+//
+// Flexible conjugate gradients on A = -L, preconditioned by one V-cycle from a
+// zero guess (FP64).  Per iteration, after z = V(r): k_fcg_dots (z.q, r.z),
+// k_fcg_beta, k_fcg_direction (q = L s for the new direction s = z + beta s_old,
+// and s.q), k_fcg_update (s and p), then the residual pass r = b - L p (MODE 2).
+// The scalars stay in device memory: scal[10] = z.q, scal[11] = r.z,
+// scal[12] = s.q, scal[14] = beta, so an iteration needs no host round trip.
+
+// Partial sums of z.q and r.z over the cells (column grid, k strided by gridDim.z).
+__global__ void __launch_bounds__(BX* BY) k_fcg_dots(const double* __restrict__ z, const double* __restrict__ q,
+                                                    const double* __restrict__ r, int nx, int ny, int nz,
+                                                    double* __restrict__ part) {
+    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+    double a = 0, b = 0;
+    if (i < nx && j < ny)
+        for (int k = blockIdx.z; k < nz; k += gridDim.z) {
+            const size_t c = cidx(i, j, k, nx, ny);
+            a += z[c] * q[c];
+            b += r[c] * z[c];
+        }
+    block_partials2(a, b, part);
+}
+
+// beta = -(z.q) / (s.q) with the previous direction's s.q; 0 before the first
+// direction (s.q is reset to 0 when a solve starts).
+__global__ void k_fcg_beta(double* __restrict__ scal) {
+    if (threadIdx.x == 0) {
+        const double sq = scal[12];
+        scal[14] = sq == 0.0 ? 0.0 : -scal[10] / sq;
+    }
+}
+
+// One plane of NC cells of the combination v = z + beta s_old (fma, the same
+// expression k_fcg_update stores), with neighbours and faces as load_cells1.
+template <int NC>
+__device__ __forceinline__ Cells1<double, NC> load_comb(const Lvl<double>& L, const double* __restrict__ z,
+                                                        const double* __restrict__ so, double beta,
+                                                        const CellOff& o, int k) {
+    const Cells1<double, NC> a = load_cells1<double, NC>(L, z, z, o, k);
+    const Cells1<double, NC> b = load_cells1<double, NC>(L, so, so, o, k);
+    Cells1<double, NC> v = a;
+#pragma unroll
+    for (int e = 0; e < NC; e++) {
+        v.p[e] = fma(beta, b.p[e], a.p[e]);
+        v.ps[e] = fma(beta, b.ps[e], a.ps[e]);
+        v.pn[e] = fma(beta, b.pn[e], a.pn[e]);
+        v.b[e] = 0.0;
+    }
+    v.pw = fma(beta, b.pw, a.pw);
+    v.pe = fma(beta, b.pe, a.pe);
+    return v;
+}
+
+// q = L s for the new direction s = z + beta s_old (s itself is not stored
+// here, so no thread overwrites a value its neighbours still read), with
+// partial sums of s.q.  nx divisible by NC; tiles as k_resid_cells.
+template <int NC>
+__global__ void __launch_bounds__(CBX* CBY) k_fcg_direction(Lvl<double> L, const double* __restrict__ z,
+                                                           const double* __restrict__ so,
+                                                           const double* __restrict__ scal, ColGrid G,
+                                                           double* __restrict__ q, double* __restrict__ part) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
+    const int I = tx * CBX + (int)(threadIdx.x % CBX), j = ty * CBY + (int)(threadIdx.x / CBX);
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int k0 = chunk * G.kc, k1 = min(nz, k0 + G.kc);
+    const double beta = scal[14];
+    double a = 0;
+    if (NC * I < nx && j < ny && k0 < k1) {
+        const size_t plane = (size_t)nx * ny;
+        const CellOff o = cell_offsets<NC>(I, j, nx, ny);
+        double vb[NC];
+        {
+            const size_t cb = (size_t)max(k0 - 1, 0) * plane + o.c;
+#pragma unroll
+            for (int e = 0; e < NC; e++) vb[e] = fma(beta, so[cb + e], z[cb + e]);
+        }
+        Cells1<double, NC> cur = load_comb<NC>(L, z, so, beta, o, k0);
+        for (int k = k0; k < k1; k++) {
+            const Cells1<double, NC> nxt = load_comb<NC>(L, z, so, beta, o, plane_above(k, nz));
+            double r[NC];
+            cells_residual(cur, vb, nxt, r);   // r = 0 - L s
+#pragma unroll
+            for (int e = 0; e < NC; e++) {
+                const double qv = -r[e];
+                q[(size_t)k * plane + o.c + e] = qv;
+                a += cur.p[e] * qv;
+                vb[e] = cur.p[e];
+            }
+            cur = nxt;
+        }
+    }
+    __shared__ double sa[CBX * CBY / 64];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+    if (threadIdx.x % 64 == 0) sa[threadIdx.x / 64] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0;
+        for (int w = 0; w < CBX * CBY / 64; w++) ta += sa[w];
+        part[2 * tile] = ta;
+        part[2 * tile + 1] = 0.0;
+    }
+}
+
+// s = z + beta s_old (stored), p += alpha s with alpha = (r.z) / (s.q).
+__global__ void k_fcg_update(const double* __restrict__ z, double* __restrict__ s, double* __restrict__ p,
+                             const double* __restrict__ scal, size_t n) {
+    const double beta = scal[14], alpha = scal[11] / scal[12];
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const double sv = fma(beta, s[t], z[t]);
+        s[t] = sv;
+        p[t] = fma(alpha, sv, p[t]);
+    }
 }
 
 }  // namespace mgk

@@ -22,7 +22,8 @@ MG_MAX_LEVELS = 24
 MG_MAX_COARSE_CELLS = 512
 MG_MAX_HISTORY = 256
 MG_NUM_TILES = 16
-KERNEL_CLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "refine", "other", "smooth_fine"]
+KERNEL_CLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "refine", "other", "smooth_fine", "krylov"]
+MG_KRYLOV_NONE, MG_KRYLOV_FCG = 0, 1
 MG_K_COUNT = len(KERNEL_CLASSES)
 
 # every function declared in include/mg.h
@@ -42,7 +43,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
                 ("n_coarsest", ctypes.c_int), ("inner_m", ctypes.c_int),
                 ("max_cycles", ctypes.c_int), ("profile", ctypes.c_int), ("tile", ctypes.c_int),
-                ("graph", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("krylov", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -133,7 +134,7 @@ class MGError(RuntimeError):
 
 
 def options(precision="fp64", nu1=2, nu2=2, n_coarsest=4, inner_m=3, max_cycles=100, profile=False,
-            tile=0, graph=False):
+            tile=0, graph=False, krylov="none"):
     o = Options()
     lib().mg_default_options(ctypes.byref(o))
     o.precision = {"fp64": MG_FP64, "fp32_refined": MG_FP32_REFINED}[precision]
@@ -141,6 +142,7 @@ def options(precision="fp64", nu1=2, nu2=2, n_coarsest=4, inner_m=3, max_cycles=
     o.profile = 1 if profile else 0
     o.tile = tile
     o.graph = 1 if graph else 0
+    o.krylov = {"none": MG_KRYLOV_NONE, "fcg": MG_KRYLOV_FCG}[krylov]
     return o
 
 
