@@ -281,6 +281,40 @@ def summarize(d):
     print("\n".join(out))
 
 
+def ratio_sweep(args):
+    """Drop splash (Fourier-perturbed film, seed 2) at n^3 (default 256) for density
+    ratios 1e1..1e5 with arithmetic and harmonic faces: FP64 V-cycle iteration,
+    FP64 flexible CG and FP32-refined V-cycles, each solved from p = 0 to the
+    tolerance (median of `steps` timed solves after `warmup`).  One JSON line per
+    case, then a summary line."""
+    import torch
+    from paper_1410_8568_amd import inputs, mg
+    n = args.n if args.n != 512 else 256
+    rows = []
+    for faces in ("arith", "harmonic"):
+        for ratio in (1e1, 1e2, 1e3, 1e4, 1e5):
+            P = inputs.drop_splash_problem(n, 0.1, (0.5, 0.5, 0.2, 0.08), ratio, 1.0, seed=2, perturb=True,
+                                           faces=faces)
+            bx, by, bz, b = mg.to_device(P)
+            p = torch.zeros_like(b)
+            row = {"n": n, "faces": faces, "ratio": ratio}
+            for name, prec, kry in (("fp64_mg", "fp64", "none"), ("fp64_fcg", "fp64", "fcg"),
+                                    ("fp32_refined_mg", "fp32_refined", "none")):
+                S = mg.Solver(bx, by, bz, precision=prec, n_coarsest=args.n_coarsest, graph=bool(args.graph),
+                              krylov=kry)
+                ms, _, st = timed_solves(S, b, p, args.steps, args.warmup, args.tol)
+                S.close()
+                last = st[-1]
+                row[name] = {"ms": ms, "cycles": last["cycles"], "gamma": last["gamma"],
+                             "rel_residual": last["rel_residual"], "rc": last["rc"]}
+            rows.append(row)
+            log(json.dumps(row))
+            del bx, by, bz, b, p
+            torch.cuda.empty_cache()
+    print(json.dumps({"sweep": "density ratio", "tol": args.tol, "n_coarsest": args.n_coarsest, "rows": rows}),
+          flush=True)
+
+
 def batch_bench(args):
     """64 uneven problems (sizes 32..128^3, 1-8 drops, ratio 10..1000): all submitted
     at once to the continuous-batching server vs solved one after another."""
@@ -400,6 +434,10 @@ def main():
     ap.add_argument("--graph", type=int, default=1, help="replay each outer iteration as a HIP graph (1) or launch eagerly (0)")
     ap.add_argument("--projection", type=int, default=1,
                     help="also time the projection step around the solve (divergence, solve, correction)")
+    ap.add_argument("--krylov", type=int, default=1,
+                    help="also time the FP64 Krylov solve (flexible CG preconditioned by one V-cycle)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="density-ratio sweep (1e1..1e5, arithmetic and harmonic faces) of the three solvers")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (counter scale)")
     ap.add_argument("--summarize", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
     ap.add_argument("--traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
@@ -421,6 +459,14 @@ def main():
         return
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.sweep:
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        import torch
+        torch.cuda.set_device(0)
+        ratio_sweep(args)
         return
     if args.batch or args.serve:
         if args.gpus != 1:
@@ -450,12 +496,12 @@ def main():
     torch.cuda.synchronize()
     N = args.n ** 3
 
-    def build(precision, profile=False):
+    def build(precision, profile=False, krylov="none"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         kw = {"inner_m": args.inner_m} if args.inner_m else {}
         S = mg.Solver(bx, by, bz, precision=precision, n_coarsest=args.n_coarsest, profile=profile,
-                      graph=args.graph and not profile, **kw)
+                      graph=args.graph and not profile, krylov=krylov, **kw)
         torch.cuda.synchronize()
         return S, (time.perf_counter() - t0) * 1e3
 
@@ -487,6 +533,22 @@ def main():
         bytes64 = sum(prof64["kernel_bytes"].values())
         res["fp64_gbps_per_vcycle"] = bytes64 / cyc64 / 1e6 / (ms64 / cyc64)
         res["fp64_cell_updates_per_s"] = N * cyc64 / (ms64 * 1e-3)
+    if args.krylov:
+        # FP64 flexible CG preconditioned by one V-cycle per iteration
+        SK, setupk = build("fp64", krylov="fcg")
+        msk, wallk, stk = timed_solves(SK, b, p, args.steps, args.warmup, args.tol)
+        lastk = stk[-1]
+        SK.close()
+        profk = profiled(lambda profile: build("fp64", profile, krylov="fcg"), b, p, args.tol)
+        kk = profk["kernel_ms"]["krylov"]
+        res["fp64_fcg"] = {"ms_per_solve": msk, "iterations": lastk["cycles"],
+                           "final_rel_residual": lastk["rel_residual"], "gamma": lastk["gamma"],
+                           "krylov_passes_gbps": profk["kernel_bytes"]["krylov"] / (kk * 1e-3) / 1e9 if kk else None,
+                           "krylov_passes_ms": kk,
+                           "vcycle_ms": sum(v for k, v in profk["kernel_ms"].items() if k != "krylov")}
+        if "fp64_ms_per_solve" in res:
+            res["fp64_fcg"]["speedup_vs_fp64_mg"] = res["fp64_ms_per_solve"] / msk
+        log(f"fp64 fcg: {msk:.2f} ms/solve, iterations {lastk['cycles']}, rho {lastk['rel_residual']:.2e}")
 
     if args.projection:
         Sp, _ = build("fp32_refined")

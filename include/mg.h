@@ -111,14 +111,14 @@ enum { MG_KRYLOV_NONE = 0, MG_KRYLOV_FCG = 1 };
 
 /* Kernel classes reported in mg_stats when options.profile is set. */
 enum {
-    MG_K_SMOOTH = 0,      /* red-black Gauss-Seidel sweeps, all levels */
+    MG_K_SMOOTH = 0,      /* red-black Gauss-Seidel sweeps on the coarse levels (level >= 1) */
     MG_K_RESTRICT = 1,    /* residual + restriction, all levels */
     MG_K_PROLONG = 2,     /* prolongation + correction, all levels */
     MG_K_COARSE = 3,      /* coarsest dense solve */
     MG_K_NORM = 4,        /* convergence residual + norm (FP64 mode) */
     MG_K_REFINE = 5,      /* FP64 refinement residual and update (refined mode) */
     MG_K_OTHER = 6,       /* projections, reductions, fills */
-    MG_K_SMOOTH_FINE = 7, /* the smoother on the finest level only (subset of MG_K_SMOOTH) */
+    MG_K_SMOOTH_FINE = 7, /* the smoother on the finest level (level 0); the classes are disjoint */
     MG_K_KRYLOV = 8,      /* Krylov vector passes: dot products, direction, update, residual */
     MG_K_COUNT = 9
 };
