@@ -42,7 +42,9 @@ _I = ctypes.POINTER(ctypes.c_int)
 class OgOpts(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("n_coarsest", ctypes.c_int),
                 ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int),
-                ("inner_m", ctypes.c_int), ("tol", ctypes.c_double), ("krylov", ctypes.c_int)]
+                ("inner_m", ctypes.c_int), ("tol", ctypes.c_double), ("krylov", ctypes.c_int),
+                ("omega", ctypes.c_double), ("restrict64", ctypes.c_int), ("gmres_m", ctypes.c_int),
+                ("gmres_tol", ctypes.c_double), ("gmres_maxit", ctypes.c_int)]
 
 
 def lib():
@@ -58,6 +60,10 @@ def lib():
         L.og_residual.argtypes = [i, i, i, _D, _D, _D, _D, _D, _D]
         L.og_rb_half.argtypes = [i, i, i, _D, _D, _D, _D, _D, i]
         L.og_restrict.argtypes = [i, i, i, _D, _D]
+        L.og_restrict64.argtypes = [i, i, i, _D, _D]
+        L.og_rb_half_sor.argtypes = [i, i, i, _D, _D, _D, _D, _D, i, ctypes.c_double]
+        L.og_gmres.argtypes = [i, i, i, _D, _D, _D, _D, _D, i, ctypes.c_double, i, _D]
+        L.og_gmres.restype = i
         L.og_prolong_add.argtypes = [i, i, i, _D, _D, _D]
         L.og_coarsen_faces.argtypes = [i, i, i, _D, _D, _D, _D, _D, _D]
         L.og_cell_weights.argtypes = [i, i, i, _D, _D, _D, _D]
@@ -121,6 +127,38 @@ def rb_half(bx, by, bz, p, b, colour):
     bx, by, bz = _c(bx), _c(by), _c(bz)
     lib().og_rb_half(nx, ny, nz, _p(bx), _p(by), _p(bz), _p(p), _p(b), int(colour))
     return p
+
+
+def rb_half_sor(bx, by, bz, p, b, colour, omega):
+    """One SOR half-sweep with factor omega over one colour (feature 5)."""
+    p = _c(p).copy()
+    b = _c(b)
+    nx, ny, nz = dims_of(p)
+    bx, by, bz = _c(bx), _c(by), _c(bz)
+    lib().og_rb_half_sor(nx, ny, nz, _p(bx), _p(by), _p(bz), _p(p), _p(b), int(colour), float(omega))
+    return p
+
+
+def restrict64(r):
+    """64-point restriction: the transpose of trilinear interpolation, times 4."""
+    r = _c(r)
+    nx, ny, nz = dims_of(r)
+    rc = np.empty((nz // 2, ny // 2, nx // 2))
+    lib().og_restrict64(nx, ny, nz, _p(r), _p(rc))
+    return rc
+
+
+def gmres(bx, by, bz, rhs, m=16, tol=1e-10, maxit=1000):
+    """Restarted GMRES(m) for L e = rhs - mean(rhs) from 0 (feature 6's coarse
+    solver).  Returns (mean-zero e, iterations, final relative residual)."""
+    rhs = _c(rhs)
+    nx, ny, nz = dims_of(rhs)
+    e = np.empty_like(rhs)
+    rr = ctypes.c_double(0)
+    bx, by, bz = _c(bx), _c(by), _c(bz)
+    it = lib().og_gmres(nx, ny, nz, _p(bx), _p(by), _p(bz), _p(rhs), _p(e), int(m), float(tol), int(maxit),
+                        ctypes.byref(rr))
+    return e, it, rr.value
 
 
 def restrict(r):
@@ -196,16 +234,21 @@ KRYLOV = {"none": 0, "fcg": 1, "cg": 2}
 
 
 def solve(bx, by, bz, b, p0=None, nu1=2, nu2=2, n_coarsest=4, max_cycles=100, tol=1e-10,
-          precision="fp64", inner_m=3, krylov="none"):
+          precision="fp64", inner_m=3, krylov="none", omega=1.0, restrict64=False, gmres_m=0,
+          gmres_tol=1e-3, gmres_maxit=200):
     """Run the oracle solve.  Returns dict(p, history, cycles, status, gamma, mean_b).
 
     krylov: "none" (V-cycle iteration), "fcg" (flexible CG preconditioned by one
-    V-cycle per iteration, FP64) or "cg" (unpreconditioned CG, for the tests)."""
+    V-cycle per iteration, FP64) or "cg" (unpreconditioned CG, for the tests).
+    Cycle variants: omega (SOR factor of the smoother), restrict64 (64-point
+    restriction), gmres_m > 0 (coarsest grid by GMRES(gmres_m) to gmres_tol
+    relative, at most gmres_maxit iterations, instead of exactly)."""
     b = _c(b)
     nx, ny, nz = dims_of(b)
     p = np.zeros_like(b) if p0 is None else _c(p0).copy()
     o = OgOpts(nu1, nu2, n_coarsest, max_cycles, {"fp64": 0, "fp32_refined": 1}[precision],
-               inner_m, tol, KRYLOV[krylov])
+               inner_m, tol, KRYLOV[krylov], float(omega), int(bool(restrict64)), int(gmres_m),
+               float(gmres_tol), int(gmres_maxit))
     hist = np.zeros(max_cycles + 1)
     ncyc = ctypes.c_int(0)
     mean_b = ctypes.c_double(0)

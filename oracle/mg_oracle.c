@@ -43,6 +43,19 @@ typedef struct {
     double *chol; /* lower Cholesky factor of B, row-major n x n */
 } coarse_t;
 
+/*
+ * Paper-faithful variants of the cycle; the defaults (omega 1, 8-child
+ * restriction, exact coarsest solve) give the standard cycle.
+ */
+typedef struct {
+    double omega;          /* SOR factor of the red-black smoother (feature 5); 1 = Gauss-Seidel */
+    int restrict64;        /* 1: 64-point restriction (transpose of trilinear interpolation) */
+    int gmres_m;           /* > 0: the coarsest grid by restarted GMRES(m) (feature 6) */
+    double gmres_tol;      /* GMRES: relative residual reduction on the coarsest grid */
+    int gmres_maxit;       /* GMRES: iteration cap */
+    const void *coarsest;  /* the coarsest FP64 level (its faces), for GMRES */
+} variant_t;
+
 #define R double
 #define SFX _d
 #include "mg_ops.inc"
@@ -319,6 +332,104 @@ static int hier_build(hier_t *H, int nx, int ny, int nz, const double *bx, const
     return coarse_setup(Lc, &H->C);
 }
 
+/*
+ * Restarted GMRES(m) on one grid (the paper's coarsest-grid solver, feature 6):
+ * L e = rhs - mean(rhs) from e = 0, Arnoldi with modified Gram-Schmidt, the
+ * least-squares problem kept triangular by Givens rotations, restart every m
+ * iterations, stop when ||rhs_bar - L e|| <= tol ||rhs_bar|| or after maxit
+ * iterations; e is returned mean-zero.  (On the singular Neumann system the
+ * Krylov space of a mean-free residual stays mean-free.)  Returns the number
+ * of iterations; *relres gets the final true relative residual.
+ */
+static int gmres_solve(const level_d *L, const double *rhs, double *e, int m, double tol, int maxit,
+                       double *relres)
+{
+    size_t n = ncell(L->nx, L->ny, L->nz);
+    double *bb = (double *)malloc(n * sizeof(double));
+    double *r = (double *)malloc(n * sizeof(double));
+    double *w = (double *)malloc(n * sizeof(double));
+    double *Vb = (double *)malloc((size_t)(m + 1) * n * sizeof(double));
+    double *H = (double *)calloc((size_t)(m + 1) * m, sizeof(double));
+    double *cs = (double *)malloc(m * sizeof(double)), *sn = (double *)malloc(m * sizeof(double));
+    double *g = (double *)malloc((m + 1) * sizeof(double)), *y = (double *)malloc(m * sizeof(double));
+    double mb = 0;
+    for (size_t t = 0; t < n; t++) mb += rhs[t];
+    mb /= (double)n;
+    double nb = 0;
+    for (size_t t = 0; t < n; t++) {
+        bb[t] = rhs[t] - mb;
+        nb += bb[t] * bb[t];
+        e[t] = 0.0;
+    }
+    nb = sqrt(nb);
+    int it = 0;
+    double beta = nb;
+    for (size_t t = 0; t < n; t++) r[t] = bb[t];
+    while (nb > 0 && beta > tol * nb && it < maxit) {
+        for (size_t t = 0; t < n; t++) Vb[t] = r[t] / beta;
+        for (int i = 0; i <= m; i++) g[i] = 0;
+        g[0] = beta;
+        int jj = 0;
+        for (int j = 0; j < m && it < maxit; j++) {
+            double *vj = Vb + (size_t)j * n;
+            apply_d(L, vj, w);
+            it++;
+            for (int i = 0; i <= j; i++) {
+                double *vi = Vb + (size_t)i * n, h = 0;
+                for (size_t t = 0; t < n; t++) h += w[t] * vi[t];
+                H[i * m + j] = h;
+                for (size_t t = 0; t < n; t++) w[t] -= h * vi[t];
+            }
+            double hn = 0;
+            for (size_t t = 0; t < n; t++) hn += w[t] * w[t];
+            hn = sqrt(hn);
+            H[(j + 1) * m + j] = hn;
+            if (hn > 0)
+                for (size_t t = 0; t < n; t++) Vb[(size_t)(j + 1) * n + t] = w[t] / hn;
+            for (int i = 0; i < j; i++) {   /* earlier rotations on the new column */
+                double a = H[i * m + j], b = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * b;
+                H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+            }
+            double a = H[j * m + j], b = H[(j + 1) * m + j], den = sqrt(a * a + b * b);
+            cs[j] = den > 0 ? a / den : 1.0;
+            sn[j] = den > 0 ? b / den : 0.0;
+            H[j * m + j] = den;
+            H[(j + 1) * m + j] = 0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            jj = j + 1;
+            if (fabs(g[j + 1]) <= tol * nb || hn == 0) break;
+        }
+        for (int i = jj - 1; i >= 0; i--) {   /* back substitution */
+            double t = g[i];
+            for (int q = i + 1; q < jj; q++) t -= H[i * m + q] * y[q];
+            y[i] = t / H[i * m + i];
+        }
+        for (int i = 0; i < jj; i++)
+            for (size_t t = 0; t < n; t++) e[t] += y[i] * Vb[(size_t)i * n + t];
+        residual_d(L, e, bb, r);
+        beta = 0;
+        for (size_t t = 0; t < n; t++) beta += r[t] * r[t];
+        beta = sqrt(beta);
+    }
+    double me = 0;
+    for (size_t t = 0; t < n; t++) me += e[t];
+    me /= (double)n;
+    for (size_t t = 0; t < n; t++) e[t] -= me;
+    if (relres) *relres = nb > 0 ? beta / nb : 0.0;
+    free(bb); free(r); free(w); free(Vb); free(H); free(cs); free(sn); free(g); free(y);
+    return it;
+}
+
+static void coarse_variant(const coarse_t *C, const variant_t *V, const double *rhs, double *e)
+{
+    if (V && V->gmres_m > 0)
+        gmres_solve((const level_d *)V->coarsest, rhs, e, V->gmres_m, V->gmres_tol, V->gmres_maxit, 0);
+    else
+        coarse_exact(C, rhs, e);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Exported primitives (for the tests)                                         */
 /* ------------------------------------------------------------------------- */
@@ -351,7 +462,16 @@ void og_rb_half(int nx, int ny, int nz, const double *bx, const double *by, cons
 {
     level_d L;
     wrap(&L, nx, ny, nz, bx, by, bz);
-    rb_half_d(&L, p, b, colour);
+    rb_half_d(&L, p, b, colour, 1.0);
+}
+
+/* One successive over-relaxation half-sweep (factor omega) over one colour. */
+void og_rb_half_sor(int nx, int ny, int nz, const double *bx, const double *by, const double *bz,
+                    double *p, const double *b, int colour, double omega)
+{
+    level_d L;
+    wrap(&L, nx, ny, nz, bx, by, bz);
+    rb_half_d(&L, p, b, colour, omega);
 }
 
 void og_restrict(int nx, int ny, int nz, const double *r, double *rc)
@@ -360,6 +480,14 @@ void og_restrict(int nx, int ny, int nz, const double *r, double *rc)
     wrap(&F, nx, ny, nz, 0, 0, 0);
     wrap(&C, nx / 2, ny / 2, nz / 2, 0, 0, 0);
     restrict8_d(&F, r, &C, rc);
+}
+
+void og_restrict64(int nx, int ny, int nz, const double *r, double *rc)
+{
+    level_d F, C;
+    wrap(&F, nx, ny, nz, 0, 0, 0);
+    wrap(&C, nx / 2, ny / 2, nz / 2, 0, 0, 0);
+    restrict64_d(&F, r, &C, rc);
 }
 
 void og_prolong_add(int cnx, int cny, int cnz, const double *a, const double *ec, double *ef)
@@ -393,6 +521,21 @@ void og_cell_weights(int nx, int ny, int nz, const double *bx, const double *by,
     wrap(&L, nx, ny, nz, bx, by, bz);
     L.a = a;
     cell_weights(&L);
+}
+
+/* GMRES(m) on one grid (faces in the face layout); returns iterations. */
+int og_gmres(int nx, int ny, int nz, const double *bx, const double *by, const double *bz, const double *rhs,
+             double *e, int m, double tol, int maxit, double *relres)
+{
+    level_d L;
+    wrap(&L, nx, ny, nz, 0, 0, 0);
+    L.bx = (double *)malloc(nfx(nx, ny, nz) * sizeof(double));
+    L.by = (double *)malloc(nfy(nx, ny, nz) * sizeof(double));
+    L.bz = (double *)malloc(nfz(nx, ny, nz) * sizeof(double));
+    copy_faces_zero_walls(&L, bx, by, bz);
+    int it = gmres_solve(&L, rhs, e, m, tol, maxit, relres);
+    free(L.bx); free(L.by); free(L.bz);
+    return it;
 }
 
 /* Exact mean-zero solution of L e = rhs - mean(rhs) on one grid (dense). */
@@ -515,6 +658,11 @@ typedef struct {
     double tol;      /* relative residual ||b_bar - L p|| / ||b_bar|| */
     int krylov;      /* FP64 only: 0 V-cycle iteration, 1 flexible CG preconditioned by one
                         V-cycle, 2 unpreconditioned CG (for the tests) */
+    double omega;    /* variants, see variant_t */
+    int restrict64;
+    int gmres_m;
+    double gmres_tol;
+    int gmres_maxit;
 } og_opts;
 
 /*
@@ -562,8 +710,8 @@ static double dot_d(const double *a, const double *b, size_t n)
  * is textbook CG.  p is made mean-zero once, at the end.  Returns the status
  * as og_solve and fills hist / *ncycles with one entry per iteration.
  */
-static int krylov_solve(hier_t *H, const double *bbar, double nb, double *p, const og_opts *o, double *hist,
-                        int *ncycles, double rho0)
+static int krylov_solve(hier_t *H, const double *bbar, double nb, double *p, const og_opts *o,
+                        const variant_t *V, double *hist, int *ncycles, double rho0)
 {
     level_d *F = &H->d[0];
     size_t n = ncell(F->nx, F->ny, F->nz);
@@ -579,7 +727,7 @@ static int krylov_solve(hier_t *H, const double *bbar, double nb, double *p, con
             memset(z, 0, n * sizeof(double));
             F->e = z;
             F->rhs = r;
-            vcycle_d(H->d, H->nlev, 0, &H->C, o->nu1, o->nu2);
+            vcycle_d(H->d, H->nlev, 0, &H->C, o->nu1, o->nu2, V);
         } else {
             for (size_t t = 0; t < n; t++) z[t] = -r[t];
         }
@@ -621,6 +769,12 @@ int og_solve(int nx, int ny, int nz, const double *bx, const double *by, const d
     }
     size_t n = ncell(nx, ny, nz);
     level_d *F = &H.d[0];
+    if (!(o->omega > 0 && o->omega < 2) || o->gmres_m < 0 || o->gmres_m > 64 ||
+        (o->gmres_m > 0 && (!(o->gmres_tol > 0) || o->gmres_maxit < 1))) {
+        hier_free(&H);
+        return -1;
+    }
+    variant_t V = {o->omega, o->restrict64, o->gmres_m, o->gmres_tol, o->gmres_maxit, &H.d[H.nlev - 1]};
 
     /* right-hand side projected onto the range of L: b_bar = b - mean(b) */
     double mean_b = sum_d(b, n) / (double)n;
@@ -655,11 +809,11 @@ int og_solve(int nx, int ny, int nz, const double *bx, const double *by, const d
             return -1;
         }
         F->e = 0;
-        status = krylov_solve(&H, bbar, nb, p, o, hist, &cyc, rho0);
+        status = krylov_solve(&H, bbar, nb, p, o, &V, hist, &cyc, rho0);
         if (cyc > 0) rho = hist[cyc];
     } else if (o->precision == 0) {
         while (status == 1 && cyc < o->max_cycles) {
-            vcycle_d(H.d, H.nlev, 0, &H.C, o->nu1, o->nu2);
+            vcycle_d(H.d, H.nlev, 0, &H.C, o->nu1, o->nu2, &V);
             double mp = sum_d(p, n) / (double)n;
             for (size_t t = 0; t < n; t++) p[t] -= mp;
             residual_d(F, p, bbar, F->r);
@@ -678,7 +832,7 @@ int og_solve(int nx, int ny, int nz, const double *bx, const double *by, const d
             double s = rms > 0 ? ldexp(1.0, (int)floor(log2(rms))) : 1.0;
             for (size_t t = 0; t < n; t++) M->rhs[t] = (float)(F->r[t] / s);
             memset(M->e, 0, n * sizeof(float));
-            for (int it = 0; it < o->inner_m; it++) vcycle_f(H.f, H.nlev, 0, &H.C, o->nu1, o->nu2);
+            for (int it = 0; it < o->inner_m; it++) vcycle_f(H.f, H.nlev, 0, &H.C, o->nu1, o->nu2, &V);
             for (size_t t = 0; t < n; t++) p[t] += s * (double)M->e[t];
             double mp = sum_d(p, n) / (double)n;
             for (size_t t = 0; t < n; t++) p[t] -= mp;
