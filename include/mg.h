@@ -99,7 +99,20 @@ typedef struct {
                         b_bar - L p is recomputed every iteration, so history and tolerance mean
                         the same as for the V-cycle iteration; stats.cycles counts iterations (one
                         V-cycle each).  Needs 32 more bytes of workspace per cell. */
+    /* Paper-faithful cycle variants (the defaults give the standard cycle).  Setting omega != 1
+       or restrict64 runs every level's smoother with the one-colour-per-pass reference kernels
+       (the fused passes implement omega = 1 and the 8-child restriction only). */
+    double omega;          /* SOR factor of the red-black smoother, 0 < omega < 2 (feature 5);
+                              default 1 = Gauss-Seidel */
+    int restrict64;        /* 1: 64-point restriction (transpose of trilinear interpolation, times 4)
+                              instead of the 8-child mean (feature 3); default 0 */
+    int coarse_gmres;      /* 0 (default): exact coarsest solve; 1..MG_GMRES_MAX_M: restarted
+                              GMRES(coarse_gmres) on the coarsest grid (feature 6), FP64 */
+    int coarse_gmres_maxit;  /* GMRES iteration cap, default 200 */
+    double coarse_gmres_tol; /* GMRES relative residual target, default 1e-3 */
 } mg_options;
+
+#define MG_GMRES_MAX_M 16
 
 enum { MG_KRYLOV_NONE = 0, MG_KRYLOV_FCG = 1 };
 

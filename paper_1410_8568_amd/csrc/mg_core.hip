@@ -97,6 +97,13 @@ mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
         set_error("option out of range");
         return MG_E_INVALID;
     }
+    if (!(o->omega > 0.0 && o->omega < 2.0) || (o->restrict64 != 0 && o->restrict64 != 1) ||
+        o->coarse_gmres < 0 || o->coarse_gmres > MG_GMRES_MAX_M ||
+        (o->coarse_gmres > 0 && (!(o->coarse_gmres_tol > 0.0) || o->coarse_gmres_maxit < 1 ||
+                                 o->coarse_gmres_maxit > 1000000))) {
+        set_error("cycle variant option out of range");
+        return MG_E_INVALID;
+    }
     if (o->krylov == MG_KRYLOV_FCG && o->precision != MG_FP64) {
         set_error("the Krylov solve runs in FP64 precision only");
         return MG_E_INVALID;
@@ -305,7 +312,13 @@ mg_status setup_launch(mg_handle* h, const double* bx, const double* by, const d
     // smoother variant (and fused pre-smoothing + restriction variant) per level
     const bool f32 = h->o.precision == MG_FP32_REFINED;
     for (int l = 0; l < MG_MAX_LEVELS; l++) h->tile[l] = h->rtile[l] = 0;
+    const bool ref_only = h->o.omega != 1.0 || h->o.restrict64;
     for (int l = 0; l + 1 < L.nlev; l++) {
+        if (ref_only) {   // the fused passes implement omega = 1 and the 8-child restriction
+            h->tile[l] = -1;
+            h->rtile[l] = 0;
+            continue;
+        }
         if (h->o.tile != 0) {
             h->tile[l] = h->o.tile;
             h->rtile[l] = (h->o.nu1 == 2 && (f32 ? has_restrict_variant<float>(h->o.tile)
@@ -441,10 +454,10 @@ static bool fused_sweep_restrict(hipStream_t s, int v, const Lvl<T>& L, const T*
 }
 
 template <class T>
-static void ref_sweep(hipStream_t s, const Lvl<T>& L, T* p, const T* b, int c0) {
+static void ref_sweep(hipStream_t s, const Lvl<T>& L, T* p, const T* b, int c0, double omega = 1.0) {
     const dim3 g = col_grid(L.nx, L.ny, L.nz), blk(BX, BY);
-    k_rb_half<T><<<g, blk, 0, s>>>(L, p, b, c0);
-    k_rb_half<T><<<g, blk, 0, s>>>(L, p, b, 1 - c0);
+    k_rb_half<T><<<g, blk, 0, s>>>(L, p, b, c0, (T)omega);
+    k_rb_half<T><<<g, blk, 0, s>>>(L, p, b, 1 - c0, (T)omega);
 }
 
 // Residual of level L restricted into rc (the next level's right-hand side),
@@ -623,7 +636,7 @@ static bool smooth(mg_handle* h, Hier<T>& H, int l, int nsweep, int c0, T*& cur,
     }
     for (; rem > 0; rem--) {
         Prof pf(h, cls, full);
-        ref_sweep<T>(s, H.L[l], cur, H.rhs[l], c0);
+        ref_sweep<T>(s, H.L[l], cur, H.rhs[l], c0, h->o.omega);
     }
     return shifted;
 }
@@ -638,6 +651,13 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
     hipStream_t s = h->stream;
     const LevelDims& d = H.d[l];
     if (l == H.nlev - 1) {
+        if (h->o.coarse_gmres > 0) {
+            Prof pf(h, MG_K_COARSE, (2.0 * d.ncell() + 3.0 * d.ncell()) * 8.0);
+            k_coarse_gmres<T><<<1, 512, 0, s>>>(Lvl<double>{d.nx, d.ny, d.nz, h->bx[l], h->by[l], h->bz[l]},
+                                               H.rhs[l], H.e[l], h->o.coarse_gmres, h->o.coarse_gmres_tol,
+                                               h->o.coarse_gmres_maxit);
+            return;
+        }
         Prof pf(h, MG_K_COARSE, (double)h->L.ncoarse * h->L.ncoarse * 8 + 2.0 * d.ncell() * sizeof(T));
         k_coarse_solve<T><<<(h->L.ncoarse + 7) / 8, 512, 0, s>>>(h->binv, h->L.ncoarse, H.rhs[l], H.e[l]);
         return;
@@ -656,6 +676,15 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
         Prof pf(h, l == 0 ? MG_K_SMOOTH_FINE : MG_K_SMOOTH, sweep_bytes + restrict_bytes);
         fused_sweep_restrict<T>(s, rtile, H.L[l], cur, alt, H.rhs[l], shift_sum, zero_init ? 1 : 0, H.rhs[l + 1]);
         std::swap(cur, alt);
+    } else if (h->o.restrict64) {
+        // residual stored in the (free) ping-pong buffer, then the 64-point restriction
+        smooth(h, H, l, h->o.nu1, 0, cur, alt, shift_sum, zero_init);
+        Prof pf(h, MG_K_RESTRICT, restrict_bytes + 2.0 * d.ncell() * sizeof(T));
+        int nbr = 0;
+        const ColGrid G = zgrid(d.nx / 2, d.ny, d.nz, false, &nbr);
+        k_resid_cells<T, 2, 2><<<nbr, CBX * CBY, 0, s>>>(H.L[l], cur, H.rhs[l], G, nullptr, nullptr, h->part,
+                                                         H.tmp[l]);
+        k_restrict64<T><<<lin_grid(c.ncell()), 256, 0, s>>>(H.tmp[l], d.nx, d.ny, d.nz, H.rhs[l + 1]);
     } else {
         smooth(h, H, l, h->o.nu1, 0, cur, alt, shift_sum, zero_init);
         Prof pf(h, MG_K_RESTRICT, restrict_bytes);
@@ -1015,6 +1044,11 @@ mg_status mg_default_options(mg_options* o) {
     o->tile = 0;
     o->graph = 0;
     o->krylov = MG_KRYLOV_NONE;
+    o->omega = 1.0;
+    o->restrict64 = 0;
+    o->coarse_gmres = 0;
+    o->coarse_gmres_maxit = 200;
+    o->coarse_gmres_tol = 1e-3;
     return MG_OK;
 }
 

@@ -408,7 +408,7 @@ __global__ void __launch_bounds__(FIN_THREADS) k_coarse_invert(Lvl<double> L, do
 // p_c = (s - b_c) / d.  Column grid, k strided by gridDim.z.
 template <class T>
 __global__ void __launch_bounds__(BX* BY) k_rb_half(Lvl<T> L, T* __restrict__ p, const T* __restrict__ b,
-                                                   int colour) {
+                                                   int colour, T omega) {
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     if (i >= L.nx || j >= L.ny) return;
     for (int k = blockIdx.z; k < L.nz; k += gridDim.z) {
@@ -416,8 +416,149 @@ __global__ void __launch_bounds__(BX* BY) k_rb_half(Lvl<T> L, T* __restrict__ p,
         T s, d;
         nbsum(L, p, i, j, k, s, d);
         size_t c = cidx(i, j, k, L.nx, L.ny);
-        p[c] = quot(s - b[c], d);
+        const T g = quot(s - b[c], d);
+        // successive over-relaxation by omega (feature 5); omega = 1 is Gauss-Seidel
+        p[c] = omega == T(1) ? g : fma(omega, g - p[c], p[c]);
     }
+}
+
+// 64-point restriction: rc(I,J,K) = 4 * sum over the fine cells 2I-1..2I+2 (and
+// likewise in y, z) of w_a w_b w_c r, w = (1, 3, 3, 1) / 8, a fine index
+// outside the grid replaced by its wall mirror (clamped): the transpose of
+// trilinear interpolation.  One thread per coarse cell; r is the level's
+// residual (stored by the residual kernel).
+template <class T>
+__global__ void k_restrict64(const T* __restrict__ r, int nx, int ny, int nz, T* __restrict__ rc) {
+    const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
+    const size_t nc = (size_t)cx * cy * cz;
+    const double w[4] = {0.125, 0.375, 0.375, 0.125};
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nc; t += (size_t)gridDim.x * blockDim.x) {
+        const int I = (int)(t % cx);
+        const size_t q = t / cx;
+        const int J = (int)(q % cy), K = (int)(q / cy);
+        T s = 0;
+        for (int c = 0; c < 4; c++) {
+            const int kk = min(max(2 * K - 1 + c, 0), nz - 1);
+            for (int b = 0; b < 4; b++) {
+                const int jj = min(max(2 * J - 1 + b, 0), ny - 1);
+                const T* row = r + ((size_t)kk * ny + jj) * nx;
+                for (int a = 0; a < 4; a++) {
+                    const int ii = min(max(2 * I - 1 + a, 0), nx - 1);
+                    s = fma((T)(w[a] * w[b] * w[c]), row[ii], s);
+                }
+            }
+        }
+        rc[t] = T(4) * s;
+    }
+}
+
+// Restarted GMRES(m) on the coarsest grid (feature 6), FP64 arithmetic,
+// n <= 512 cells, one workgroup of 512 threads (thread t owns cell t): solve
+// L e = r - mean(r) from e = 0 with Arnoldi (modified Gram-Schmidt, the basis
+// in LDS, where the operator reads neighbours), the least-squares problem kept
+// triangular by Givens rotations, restart every m iterations, stop when the
+// residual is <= tol of the mean-free right-hand side or after maxit
+// iterations; e is returned mean-zero.  Every loop test reads values all
+// threads share, so the barriers are uniform.
+constexpr int GMRES_MAX_M = 16;
+template <class T>
+__global__ void __launch_bounds__(512) k_coarse_gmres(Lvl<double> L, const T* __restrict__ rin, T* __restrict__ eout,
+                                                     int m, double tol, int maxit) {
+    __shared__ double V[GMRES_MAX_M + 1][512];
+    __shared__ double H[(GMRES_MAX_M + 1) * GMRES_MAX_M];
+    __shared__ double cs[GMRES_MAX_M], sn[GMRES_MAX_M], g[GMRES_MAX_M + 1], y[GMRES_MAX_M];
+    __shared__ double red[8];
+    const int t = threadIdx.x;
+    const int nx = L.nx, ny = L.ny, n = nx * ny * L.nz;
+    const bool act = t < n;
+    auto bsum = [&](double v) {
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (t % 64 == 0) red[t / 64] = v;
+        __syncthreads();
+        double s = 0;
+        for (int w = 0; w < 8; w++) s += red[w];
+        __syncthreads();
+        return s;
+    };
+    // this cell's faces and neighbour indices (a neighbour across a wall is the
+    // cell itself, multiplied by a zero face)
+    double w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;
+    int nw = t, ne = t, ns = t, nn = t, nd = t, nu = t;
+    if (act) {
+        const int i = t % nx, j = (t / nx) % ny, k = t / (nx * ny);
+        faces6(L, i, j, k, (size_t)t, w0, w1, w2, w3, w4, w5);
+        if (i > 0) nw = t - 1;
+        if (i < nx - 1) ne = t + 1;
+        if (j > 0) ns = t - nx;
+        if (j < ny - 1) nn = t + nx;
+        if (k > 0) nd = t - nx * ny;
+        if (k < L.nz - 1) nu = t + nx * ny;
+    }
+    const double diag = stencil_diag(w0, w1, w2, w3, w4, w5);
+    auto apply = [&](const double* x) {   // (L x)_t; x in LDS, synchronised
+        if (!act) return 0.0;
+        const double s = stencil_sum(w0, w1, w2, w3, w4, w5, x[nw], x[ne], x[ns], x[nn], x[nd], x[nu]);
+        return fma(-diag, x[t], s);
+    };
+    const double bt = act ? (double)rin[t] : 0.0;
+    const double mb = bsum(bt) / n;
+    const double bb = act ? bt - mb : 0.0;
+    const double nb = sqrt(bsum(bb * bb));
+    double x = 0.0, r = bb, beta = nb;
+    int it = 0;
+    while (nb > 0.0 && beta > tol * nb && it < maxit) {
+        V[0][t] = r / beta;
+        if (t == 0) {
+            for (int i = 0; i <= m; i++) g[i] = 0.0;
+            g[0] = beta;
+        }
+        __syncthreads();
+        int jj = 0;
+        for (int j = 0; j < m && it < maxit; j++) {
+            double w = apply(V[j]);
+            it++;
+            for (int i = 0; i <= j; i++) {
+                const double h = bsum(w * V[i][t]);
+                w -= h * V[i][t];
+                if (t == 0) H[i * m + j] = h;
+            }
+            const double hn = sqrt(bsum(w * w));
+            V[j + 1][t] = hn > 0.0 ? w / hn : 0.0;
+            if (t == 0) {
+                H[(j + 1) * m + j] = hn;
+                for (int i = 0; i < j; i++) {   // earlier rotations on the new column
+                    const double a = H[i * m + j], b = H[(i + 1) * m + j];
+                    H[i * m + j] = cs[i] * a + sn[i] * b;
+                    H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+                }
+                const double a = H[j * m + j], b = hn, den = sqrt(a * a + b * b);
+                cs[j] = den > 0.0 ? a / den : 1.0;
+                sn[j] = den > 0.0 ? b / den : 0.0;
+                H[j * m + j] = den;
+                H[(j + 1) * m + j] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+            }
+            __syncthreads();
+            jj = j + 1;
+            if (fabs(g[j + 1]) <= tol * nb || hn == 0.0) break;
+        }
+        if (t == 0)
+            for (int i = jj - 1; i >= 0; i--) {   // back substitution
+                double s = g[i];
+                for (int q = i + 1; q < jj; q++) s -= H[i * m + q] * y[q];
+                y[i] = H[i * m + i] != 0.0 ? s / H[i * m + i] : 0.0;
+            }
+        __syncthreads();
+        for (int i = 0; i < jj; i++) x += y[i] * V[i][t];
+        __syncthreads();
+        V[0][t] = x;   // the true residual of the new iterate
+        __syncthreads();
+        r = act ? bb - apply(V[0]) : 0.0;
+        beta = sqrt(bsum(r * r));
+    }
+    const double me = bsum(act ? x : 0.0) / n;
+    if (act) eout[t] = (T)(x - me);
 }
 
 // Exact coarsest solve e = -B^{-1} (r - mean r), FP64 arithmetic, n <= 512.

@@ -43,7 +43,9 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
                 ("n_coarsest", ctypes.c_int), ("inner_m", ctypes.c_int),
                 ("max_cycles", ctypes.c_int), ("profile", ctypes.c_int), ("tile", ctypes.c_int),
-                ("graph", ctypes.c_int), ("krylov", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("krylov", ctypes.c_int), ("omega", ctypes.c_double),
+                ("restrict64", ctypes.c_int), ("coarse_gmres", ctypes.c_int), ("coarse_gmres_maxit", ctypes.c_int),
+                ("coarse_gmres_tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -134,7 +136,8 @@ class MGError(RuntimeError):
 
 
 def options(precision="fp64", nu1=2, nu2=2, n_coarsest=4, inner_m=3, max_cycles=100, profile=False,
-            tile=0, graph=False, krylov="none"):
+            tile=0, graph=False, krylov="none", omega=1.0, restrict64=False, coarse_gmres=0,
+            coarse_gmres_tol=1e-3, coarse_gmres_maxit=200):
     o = Options()
     lib().mg_default_options(ctypes.byref(o))
     o.precision = {"fp64": MG_FP64, "fp32_refined": MG_FP32_REFINED}[precision]
@@ -143,6 +146,11 @@ def options(precision="fp64", nu1=2, nu2=2, n_coarsest=4, inner_m=3, max_cycles=
     o.tile = tile
     o.graph = 1 if graph else 0
     o.krylov = {"none": MG_KRYLOV_NONE, "fcg": MG_KRYLOV_FCG}[krylov]
+    o.omega = omega
+    o.restrict64 = 1 if restrict64 else 0
+    o.coarse_gmres = coarse_gmres
+    o.coarse_gmres_tol = coarse_gmres_tol
+    o.coarse_gmres_maxit = coarse_gmres_maxit
     return o
 
 
