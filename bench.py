@@ -315,6 +315,45 @@ def ratio_sweep(args):
           flush=True)
 
 
+VARIANT_SET = [
+    ("default", {}),
+    ("sor_1.1", {"omega": 1.1}),
+    ("sor_1.2", {"omega": 1.2}),
+    ("sor_1.3", {"omega": 1.3}),
+    ("restrict64", {"restrict64": True}),
+    ("coarse_gmres16_1e-2", {"coarse_gmres": 16, "coarse_gmres_tol": 1e-2, "coarse_gmres_maxit": 500}),
+    ("coarse_gmres16_1e-6", {"coarse_gmres": 16, "coarse_gmres_tol": 1e-6, "coarse_gmres_maxit": 2000}),
+    ("sor_1.2+restrict64", {"omega": 1.2, "restrict64": True}),
+]
+
+
+def variant_bench(args):
+    """The paper-faithful cycle variants on the benchmark's drop-splash field:
+    cycles, gamma and time to the tolerance for the FP64 and FP32-refined
+    solvers (a non-default smoother or restriction runs the reference
+    one-colour kernels, so its time is not comparable with the fused default;
+    cycles and gamma are).  One JSON line per variant, then a summary line."""
+    import torch
+    from paper_1410_8568_amd import inputs, mg
+    P = inputs.config2(args.n)
+    bx, by, bz, b = mg.to_device(P)
+    p = torch.zeros_like(b)
+    rows = []
+    for name, kw in VARIANT_SET:
+        row = {"variant": name, "options": kw}
+        for prec in ("fp64", "fp32_refined"):
+            S = mg.Solver(bx, by, bz, precision=prec, n_coarsest=args.n_coarsest, graph=bool(args.graph), **kw)
+            ms, _, st = timed_solves(S, b, p, args.steps, args.warmup, args.tol)
+            S.close()
+            last = st[-1]
+            row[prec] = {"ms": ms, "cycles": last["cycles"], "outer": last["outer"], "gamma": last["gamma"],
+                         "rel_residual": last["rel_residual"]}
+        rows.append(row)
+        log(json.dumps(row))
+    print(json.dumps({"variants": f"drop splash {args.n}^3, ratio 1000, coarsest {args.n_coarsest}^3",
+                      "tol": args.tol, "rows": rows}), flush=True)
+
+
 def batch_bench(args):
     """64 uneven problems (sizes 32..128^3, 1-8 drops, ratio 10..1000): all submitted
     at once to the continuous-batching server vs solved one after another."""
@@ -438,6 +477,9 @@ def main():
                     help="also time the FP64 Krylov solve (flexible CG preconditioned by one V-cycle)")
     ap.add_argument("--sweep", action="store_true",
                     help="density-ratio sweep (1e1..1e5, arithmetic and harmonic faces) of the three solvers")
+    ap.add_argument("--variants", action="store_true",
+                    help="cycles, gamma and time of the paper-faithful cycle variants (SOR, 64-point restriction, "
+                         "coarse GMRES)")
     ap.add_argument("--calibrate-copy", action="store_true", help="run a 1 GiB device copy (counter scale)")
     ap.add_argument("--summarize", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
     ap.add_argument("--traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
@@ -459,6 +501,14 @@ def main():
         return
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.variants:
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        import torch
+        torch.cuda.set_device(0)
+        variant_bench(args)
         return
     if args.sweep:
         if args.gpus != 1:
