@@ -75,6 +75,8 @@ def lib():
         L.og_solve.restype = i
         L.og_divergence.argtypes = [i, i, i, _D, _D, _D, ctypes.c_double, _D]
         L.og_correct_velocity.argtypes = [i, i, i, _D, _D, _D, _D, ctypes.c_double, _D, _D, _D]
+        L.og_faces_from_levelset.argtypes = [i, i, i, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, i,
+                                             _D, _D, _D]
         L.og_num_threads.restype = i
         L.og_last_timing.argtypes = [_D, _D]
         _lib = L
@@ -296,6 +298,18 @@ def project(bx, by, bz, u, v, w, dt, h, tol=1e-10, **solve_kw):
     res = solve(bx, by, bz, b, tol=tol, **solve_kw)
     un, vn, wn = correct_velocity(bx, by, bz, res["p"], u, v, w, dt / h)
     return dict(b=b, p=res["p"], u=un, v=vn, w=wn, solve=res)
+
+
+def faces_from_levelset(phi, rho_l, rho_g, eps, faces="arith"):
+    """Face coefficients (walls 0) from a level set: smoothed Heaviside of
+    half-width eps -> rho (eq. 8) -> alpha = 1/rho -> arithmetic or harmonic
+    (eqs. 11-12) face mean.  Returns (bx, by, bz)."""
+    phi = _c(phi)
+    nx, ny, nz = dims_of(phi)
+    bx = np.empty((nz, ny, nx + 1)); by = np.empty((nz, ny + 1, nx)); bz = np.empty((nz + 1, ny, nx))
+    lib().og_faces_from_levelset(nx, ny, nz, _p(phi), float(rho_l), float(rho_g), float(eps),
+                                 {"arith": 0, "harmonic": 1}[faces], _p(bx), _p(by), _p(bz))
+    return bx, by, bz
 
 
 def last_timing():

@@ -646,6 +646,76 @@ void og_correct_velocity(int nx, int ny, int nz, const double *bx, const double 
 }
 
 /* ------------------------------------------------------------------------- */
+/* Material properties from a level-set field (Sec. 2.2, eq. 8)                */
+/* ------------------------------------------------------------------------- */
+/*
+ * The indicator I is a numerical Heaviside that goes from 0 to 1 over three to
+ * four cells; from a level set phi (positive in the liquid) it is the smoothed
+ * Heaviside of half-width eps:
+ *     I = 0 (phi <= -eps),  1 (phi >= eps),  (1/2)(1 + x + sin(pi x)/pi), x = phi/eps
+ * (the band edges take their exact values; the formula would leave a rounding
+ * residue of sin(pi) there).
+ * Eq. (8) mixes the density linearly, rho = rho_g + (rho_l - rho_g) I, the
+ * pressure equation's coefficient is alpha = 1/rho, and each interior face gets
+ * the arithmetic mean of its two cells' alpha or, with harmonic = 1, the
+ * harmonic mean of eqs. (11)-(12), 2 a b / (a + b).  Wall faces are 0.
+ * Evaluation order (fixed): x = phi/eps, I = 0.5 * ((1 + x) + sin(pi * x) / pi),
+ * alpha = 1 / (rho_g + (rho_l - rho_g) * I), arithmetic 0.5 * (a + b),
+ * harmonic (2 * a * b) / (a + b).
+ */
+static const double OG_PI = 3.14159265358979323846;
+
+static double cell_alpha(double phi, double rho_l, double rho_g, double eps)
+{
+    double ind;
+    if (phi <= -eps) ind = 0.0;
+    else if (phi >= eps) ind = 1.0;
+    else {
+        double x = phi / eps;
+        ind = 0.5 * ((1.0 + x) + sin(OG_PI * x) / OG_PI);
+    }
+    return 1.0 / (rho_g + (rho_l - rho_g) * ind);
+}
+
+static double face_mean(double a, double b, int harmonic)
+{
+    return harmonic ? (2.0 * a * b) / (a + b) : 0.5 * (a + b);
+}
+
+void og_faces_from_levelset(int nx, int ny, int nz, const double *phi, double rho_l, double rho_g, double eps,
+                            int harmonic, double *bx, double *by, double *bz)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++) {
+            for (int i = 0; i <= nx; i++) {
+                size_t f = fx_at(nx, ny, i, j, k);
+                bx[f] = (i == 0 || i == nx) ? 0.0
+                        : face_mean(cell_alpha(phi[c_at(nx, ny, i - 1, j, k)], rho_l, rho_g, eps),
+                                    cell_alpha(phi[c_at(nx, ny, i, j, k)], rho_l, rho_g, eps), harmonic);
+            }
+        }
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j <= ny; j++)
+            for (int i = 0; i < nx; i++) {
+                size_t f = fy_at(nx, ny, i, j, k);
+                by[f] = (j == 0 || j == ny) ? 0.0
+                        : face_mean(cell_alpha(phi[c_at(nx, ny, i, j - 1, k)], rho_l, rho_g, eps),
+                                    cell_alpha(phi[c_at(nx, ny, i, j, k)], rho_l, rho_g, eps), harmonic);
+            }
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k <= nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                size_t f = fz_at(nx, ny, i, j, k);
+                bz[f] = (k == 0 || k == nz) ? 0.0
+                        : face_mean(cell_alpha(phi[c_at(nx, ny, i, j, k - 1)], rho_l, rho_g, eps),
+                                    cell_alpha(phi[c_at(nx, ny, i, j, k)], rho_l, rho_g, eps), harmonic);
+            }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Driver                                                                      */
 /* ------------------------------------------------------------------------- */
 

@@ -30,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "smoothed_heaviside", "cell_centres", "faces_from_alpha",
-    "divergence_rhs", "velocity_field", "normal_rhs", "sphere_problem", "drop_splash_problem",
+    "divergence_rhs", "velocity_field", "normal_rhs", "drop_splash_levelset", "sphere_problem", "drop_splash_problem",
     "config0", "config1", "config2", "batch_problems", "request_stream",
     "layered_problem", "constant_problem",
 ]
@@ -221,6 +221,25 @@ def drop_splash_problem(n=256, film_depth=0.1, drop=(0.5, 0.5, 0.2, 0.08),
     return Problem(dims, bx, by, bz, b,
                    dict(kind="drop_splash", n=n, film=film_depth, drop=drop,
                         ratio=rho_l / rho_g, seed=seed, perturbed=perturb))
+
+
+def drop_splash_levelset(n=256, film_depth=0.1, drop=(0.5, 0.5, 0.2, 0.08), seed=1, perturb=False):
+    """The level set phi (signed distance, positive in the liquid) of the drop-splash
+    scene of ``drop_splash_problem`` with the same arguments (the same Fourier draws
+    when ``perturb``), as one [nz][ny][nx] array, for building the properties on
+    the device."""
+    dims = (n, n, n) if np.ndim(n) == 0 else tuple(n)
+    rng = np.random.default_rng(seed)
+    film = film_depth
+    if perturb:
+        c = rng.standard_normal((8, 8))
+        xc = cell_centres(dims[0])
+        yc = cell_centres(dims[1])
+        m = np.arange(1, 9)
+        P = np.einsum("mn,mx,ny->yx", c, np.cos(np.pi * m[:, None] * xc[None, :]),
+                      np.cos(np.pi * m[:, None] * yc[None, :]))
+        film = film_depth + 0.01 * P / np.max(np.abs(P))
+    return _geometry_phi(dims, [drop], film)(cell_centres(dims[2]))
 
 
 def config0() -> Problem:

@@ -1,0 +1,64 @@
+"""Pins of the oracle's material-property generation from a level set (Sec.
+2.2: the indicator as a smoothed Heaviside over three to four cells, eq. 8
+for the density, alpha = 1/rho, eqs. 11-12 for the harmonic face mean)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1410_8568_amd import inputs
+
+RL, RG = 1000.0, 1.0
+
+
+def layered(phi_z, nx=3, ny=2):
+    """phi depending on z only: every x-face of plane k is the cell alpha there."""
+    nz = len(phi_z)
+    return np.broadcast_to(np.asarray(phi_z, float)[:, None, None], (nz, ny, nx)).copy()
+
+
+@pytest.mark.parametrize("faces", ["arith", "harmonic"])
+def test_uniform_fields_give_the_pure_phases_and_the_midpoint(faces):
+    eps = 0.1
+    for phi, alpha in ((2 * eps, 1 / RL), (-2 * eps, 1 / RG), (0.0, 2 / (RL + RG))):
+        bx, by, bz = oracle.faces_from_levelset(np.full((4, 3, 5), phi), RL, RG, eps, faces)
+        for b, inner in ((bx, np.s_[:, :, 1:-1]), (by, np.s_[:, 1:-1, :]), (bz, np.s_[1:-1])):
+            assert np.allclose(b[inner], alpha, rtol=1e-15, atol=0)
+        assert not bx[:, :, [0, -1]].any() and not by[:, [0, -1], :].any() and not bz[[0, -1]].any()
+
+
+def test_indicator_shape():
+    """I(phi) + I(-phi) = 1, I(0) = 1/2, I' (0) = 1/eps, 0 and 1 outside the band,
+    continuous at its edges, monotone: read through rho = 1/alpha of a layered field."""
+    eps = 0.25
+    z = np.array([-0.3, -eps, -0.2, -0.1, -1e-6, 0.0, 1e-6, 0.1, 0.2, eps, 0.3])
+    bx, _, _ = oracle.faces_from_levelset(layered(z), RL, RG, eps)
+    rho = 1.0 / bx[:, 0, 1]
+    ind = (rho - RG) / (RL - RG)
+    assert np.allclose(ind + ind[::-1], 1.0, atol=1e-13)
+    assert abs(ind[5] - 0.5) <= 1e-15
+    assert ind[0] == ind[1] == 0.0 and ind[-1] == ind[-2] == 1.0
+    assert np.all(np.diff(ind[1:-1]) > 0)
+    assert abs((ind[6] - ind[4]) / 2e-6 - 1 / eps) <= 1e-6 / eps
+    # closed form inside the band: (1/2)(1 + x + sin(pi x)/pi)
+    x = z[2:9] / eps
+    assert np.allclose(ind[2:9], 0.5 * (1 + x + np.sin(np.pi * x) / np.pi), rtol=0, atol=1e-13)
+
+
+def test_face_means_are_eqs_11_12_and_arithmetic():
+    phi = np.array([[[1.0, -1.0]]])   # liquid cell next to a gas cell
+    ax, _, _ = oracle.faces_from_levelset(phi, RL, RG, 0.1, "arith")
+    hx, _, _ = oracle.faces_from_levelset(phi, RL, RG, 0.1, "harmonic")
+    a, b = 1 / RL, 1 / RG
+    assert ax[0, 0, 1] == 0.5 * (a + b)
+    assert abs(hx[0, 0, 1] - 2 * a * b / (a + b)) <= 1e-16
+    assert abs(hx[0, 0, 1] - 2 / (RL + RG)) <= 1e-16   # harmonic mean of alpha = 1 / mean of rho
+
+
+@pytest.mark.parametrize("faces", ["arith", "harmonic"])
+def test_matches_the_host_generator(faces):
+    P = inputs.drop_splash_problem((40), 0.1, (0.5, 0.5, 0.2, 0.08), RL, RG, seed=2, perturb=True, faces=faces)
+    phi = inputs.drop_splash_levelset(40, seed=2, perturb=True)
+    got = oracle.faces_from_levelset(phi, RL, RG, 1.5 / 40, faces)
+    for g, ref in zip(got, (P.bx, P.by, P.bz)):
+        assert np.array_equal(g == 0, ref == 0)
+        assert np.max(np.abs(g - ref)) <= 1e-13 * np.abs(ref).max()
