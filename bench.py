@@ -150,6 +150,29 @@ def projection_bench(S, n, steps, warmup, tol, dev):
     return out
 
 
+def levelset_bench(n, dev):
+    """The face coefficients of the benchmark field built on the device from its
+    level set (drop splash, Fourier-perturbed film, seed 2, eps = 1.5 h): 10
+    back-to-back launches timed with HIP events on the launch stream; algorithmic
+    bytes 8 (phi) + 24 (three faces) per cell."""
+    import torch
+    from paper_1410_8568_amd import inputs, mg
+    phi = torch.from_numpy(inputs.drop_splash_levelset(n, seed=2, perturb=True)).to(dev)
+    out = mg.faces_from_levelset(phi, 1000.0, 1.0, 1.5 / n)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        mg.faces_from_levelset(phi, 1000.0, 1.0, 1.5 / n, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    byt = 32 * n ** 3
+    del phi, out
+    return {"avg_launch_ms": ms, "bytes_per_launch": byt, "achieved_gbps": byt / (ms * 1e-3) / 1e9,
+            "frac": byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+
+
 def kernel_source_sha():
     import hashlib
     h = hashlib.sha256()
@@ -605,6 +628,10 @@ def main():
         res["projection_step"] = projection_bench(Sp, args.n, args.steps, args.warmup, args.tol, dev)
         Sp.close()
         log(f"projection step: {json.dumps(res['projection_step'])}")
+
+    if args.projection:
+        res["levelset_faces"] = levelset_bench(args.n, dev)
+        log(f"faces from the level set: {json.dumps(res['levelset_faces'])}")
 
     # dominant kernel of the timed (FP32-refined) step, from the profiled solve
     kms = prof32["kernel_ms"]

@@ -276,6 +276,29 @@ mg_status mg_project(mg_handle *h, double *u, double *v, double *w, double dt, d
                      double *p, double tol, mg_stats *st, void *stream);
 
 /* ------------------------------------------------------------------------- */
+/* Material properties from a level set                                       */
+/* ------------------------------------------------------------------------- */
+/*
+ * Face coefficients for mg_setup built on the device from a level set phi
+ * (Sec. 2.2): the indicator is the smoothed Heaviside of half-width eps (the
+ * paper resolves it over three to four cells; eps = 1.5 h is typical),
+ *     I = 0 (phi <= -eps), 1 (phi >= eps), (1/2)(1 + x + sin(pi x)/pi), x = phi/eps,
+ * the density rho = rho_g + (rho_l - rho_g) I (eq. 8), alpha = 1/rho, and each
+ * interior face gets the arithmetic mean of its two cells' alpha (harmonic = 0)
+ * or their harmonic mean, eqs. (11)-(12) (harmonic = 1).  Wall faces are 0.
+ * Fixed evaluation order without fused multiply-adds: x = phi/eps,
+ * I = 0.5*((1 + x) + sin(pi*x)/pi), alpha = 1/(rho_g + (rho_l - rho_g)*I),
+ * 0.5*(a + b) or (2*a*b)/(a + b).
+ * g: cells per direction (each >= 1).  phi: device double [nz][ny][nx], positive
+ * in the liquid.  bx, by, bz: device double face arrays (layout above), every
+ * entry written.  rho_l, rho_g, eps finite and > 0.  Asynchronous on `stream`.
+ * Errors: MG_E_INVALID (NULL grid/array, a dimension < 1, a bad density, eps or
+ * harmonic flag, a grid too large for one launch), MG_E_HIP (launch failure).
+ */
+mg_status mg_faces_from_levelset(const mg_grid *g, const double *phi, double rho_l, double rho_g, double eps,
+                                 int harmonic, double *bx, double *by, double *bz, void *stream);
+
+/* ------------------------------------------------------------------------- */
 /* Continuous-batching solve server                                           */
 /* ------------------------------------------------------------------------- */
 

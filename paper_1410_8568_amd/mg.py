@@ -31,7 +31,7 @@ EXPORTS = [
     "mg_default_options", "mg_workspace_bytes", "mg_setup", "mg_solve", "mg_destroy",
     "mg_level_dims", "mg_level_tile", "mg_copy_level", "mg_server_create", "mg_batch_submit", "mg_poll",
     "mg_server_destroy", "mg_status_string", "mg_last_error", "mg_divergence", "mg_correct_velocity",
-    "mg_project",
+    "mg_project", "mg_faces_from_levelset",
 ]
 
 
@@ -115,6 +115,7 @@ def lib():
     L.mg_divergence.argtypes = [ctypes.POINTER(Grid), vp, vp, vp, d, vp, vp]
     L.mg_correct_velocity.argtypes = [vp, vp, d, vp, vp, vp, vp]
     L.mg_project.argtypes = [vp, vp, vp, vp, d, d, vp, vp, d, ctypes.POINTER(Stats), vp]
+    L.mg_faces_from_levelset.argtypes = [ctypes.POINTER(Grid), vp, d, d, d, i, vp, vp, vp, vp]
     L.mg_status_string.argtypes = [i]
     L.mg_status_string.restype = ctypes.c_char_p
     L.mg_last_error.argtypes = []
@@ -203,6 +204,28 @@ def divergence(u, v, w, scale, b=None, stream=None):
     if rc != MG_OK:
         raise MGError(rc, "mg_divergence")
     return b
+
+
+def faces_from_levelset(phi, rho_l, rho_g, eps, faces="arith", out=None, stream=None):
+    """Face coefficients (bx, by, bz) from a device level set phi [nz][ny][nx]
+    (positive in the liquid): smoothed Heaviside of half-width eps, density by
+    eq. (8), alpha = 1/rho, arithmetic or harmonic (eqs. 11-12) face mean, walls 0.
+    Asynchronous on the stream; ``out`` may supply the three face tensors."""
+    import torch
+    nz, ny, nx = phi.shape
+    _check_field(phi, (nz, ny, nx), "phi")
+    if out is None:
+        out = (torch.empty((nz, ny, nx + 1), dtype=torch.float64, device=phi.device),
+               torch.empty((nz, ny + 1, nx), dtype=torch.float64, device=phi.device),
+               torch.empty((nz + 1, ny, nx), dtype=torch.float64, device=phi.device))
+    _check_velocity(*out, (nx, ny, nz))
+    g = Grid(nx, ny, nz)
+    rc = lib().mg_faces_from_levelset(ctypes.byref(g), _ptr(phi), ctypes.c_double(rho_l), ctypes.c_double(rho_g),
+                                      ctypes.c_double(eps), {"arith": 0, "harmonic": 1}[faces], _ptr(out[0]),
+                                      _ptr(out[1]), _ptr(out[2]), _stream(stream))
+    if rc != MG_OK:
+        raise MGError(rc, "mg_faces_from_levelset")
+    return out
 
 
 class Solver:
