@@ -312,9 +312,8 @@ mg_status setup_launch(mg_handle* h, const double* bx, const double* by, const d
     // smoother variant (and fused pre-smoothing + restriction variant) per level
     const bool f32 = h->o.precision == MG_FP32_REFINED;
     for (int l = 0; l < MG_MAX_LEVELS; l++) h->tile[l] = h->rtile[l] = 0;
-    const bool ref_only = h->o.omega != 1.0 || h->o.restrict64;
     for (int l = 0; l + 1 < L.nlev; l++) {
-        if (ref_only) {   // the fused passes implement omega = 1 and the 8-child restriction
+        if (h->o.restrict64) {   // the fused passes restrict with the 8-child mean only
             h->tile[l] = -1;
             h->rtile[l] = 0;
             continue;
@@ -374,7 +373,7 @@ struct Hier {
 
 template <class T, int TX, int TY, int NSW, bool RES = false>
 static void launch_sweep(hipStream_t s, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0, int target,
-                         const double* shift_sum, int zero_in, T* rc = nullptr) {
+                         const double* shift_sum, int zero_in, T* rc, double omega) {
     const int gx = (L.nx + TX - 1) / TX, gy = (L.ny + TY - 1) / TY;
     const int tiles = gx * gy;
     // chunks of >= 8 planes, so the redundant planes at chunk ends stay a small fraction
@@ -383,8 +382,12 @@ static void launch_sweep(hipStream_t s, const Lvl<T>& L, const T* pin, T* pout, 
     if (RES && (kc & 1)) kc++;   // the restriction pairs planes 2K, 2K+1 within a chunk
     chunks = (L.nz + kc - 1) / kc;
     constexpr int NT = (TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES ? 2 : 0));
-    k_rb_sweep<T, TX, TY, NSW, RES><<<dim3(tiles * chunks), NT, 0, s>>>(
-        L, pin, pout, b, c0, kc, gx, gy, shift_sum, (double)L.nx * L.ny * L.nz, zero_in, rc);
+    if (omega != 1.0)   // successive over-relaxation (a separate instantiation)
+        k_rb_sweep<T, TX, TY, NSW, RES, true><<<dim3(tiles * chunks), NT, 0, s>>>(
+            L, pin, pout, b, c0, kc, gx, gy, shift_sum, (double)L.nx * L.ny * L.nz, zero_in, rc, (T)omega);
+    else
+        k_rb_sweep<T, TX, TY, NSW, RES, false><<<dim3(tiles * chunks), NT, 0, s>>>(
+            L, pin, pout, b, c0, kc, gx, gy, shift_sum, (double)L.nx * L.ny * L.nz, zero_in, rc, T(1));
 }
 
 // Sweeps done by one pass of fused variant v (1..MG_NUM_TILES).
@@ -400,26 +403,26 @@ static bool variant_native(int v) {
 // Fused sweep variant v in 1..MG_NUM_TILES: one pass doing sweeps_per_pass(v) sweeps.
 template <class T>
 static void fused_sweep(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0,
-                        const double* shift_sum = nullptr, int zero_in = 0) {
+                        const double* shift_sum = nullptr, int zero_in = 0, double omega = 1.0) {
     const int target = ((v - 1) & 1) ? 4096 : 1024;
     switch ((v - 1) >> 1) {
-        case 0: launch_sweep<T, 64, 8, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in); break;
-        case 1: launch_sweep<T, 128, 4, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in); break;
-        case 2: launch_sweep<T, 128, 8, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in); break;
-        case 3: launch_sweep<T, 64, 16, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in); break;
-        case 4: launch_sweep<T, 64, 4, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in); break;
-        case 5: launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in); break;
+        case 0: launch_sweep<T, 64, 8, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega); break;
+        case 1: launch_sweep<T, 128, 4, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega); break;
+        case 2: launch_sweep<T, 128, 8, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega); break;
+        case 3: launch_sweep<T, 64, 16, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega); break;
+        case 4: launch_sweep<T, 64, 4, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega); break;
+        case 5: launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega); break;
         case 6:
             if constexpr (sizeof(T) == 4)
-                launch_sweep<T, 128, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in);
+                launch_sweep<T, 128, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega);
             else
-                launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in);
+                launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega);
             break;
         default:
             if constexpr (sizeof(T) == 4)
-                launch_sweep<T, 64, 16, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in);
+                launch_sweep<T, 64, 16, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega);
             else
-                launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in);
+                launch_sweep<T, 64, 8, 2>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega);
             break;
     }
 }
@@ -438,14 +441,14 @@ static bool has_restrict_variant(int v) {
 // (nothing launched) when v has no such pass.
 template <class T>
 static bool fused_sweep_restrict(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b,
-                                 const double* shift_sum, int zero_in, T* rc) {
+                                 const double* shift_sum, int zero_in, T* rc, double omega = 1.0) {
     const int target = ((v - 1) & 1) ? 4096 : 1024;
     switch ((v - 1) >> 1) {
-        case 4: launch_sweep<T, 64, 4, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc); return true;
-        case 5: launch_sweep<T, 64, 8, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc); return true;
+        case 4: launch_sweep<T, 64, 4, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc, omega); return true;
+        case 5: launch_sweep<T, 64, 8, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc, omega); return true;
         case 7:
             if constexpr (sizeof(T) == 4) {
-                launch_sweep<T, 64, 16, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc);
+                launch_sweep<T, 64, 16, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc, omega);
                 return true;
             }
             return false;
@@ -628,7 +631,8 @@ static bool smooth(mg_handle* h, Hier<T>& H, int l, int nsweep, int c0, T*& cur,
             // algorithmic bytes: one sweep's worth per sweep done (less the
             // iterate's read when it starts from zero)
             Prof pf(h, cls, spp * full - (zero_in ? (double)d.ncell() * sizeof(T) : 0.0));
-            fused_sweep<T>(s, tile, H.L[l], cur, alt, H.rhs[l], c0, shifted ? nullptr : shift_sum, zero_in ? 1 : 0);
+            fused_sweep<T>(s, tile, H.L[l], cur, alt, H.rhs[l], c0, shifted ? nullptr : shift_sum, zero_in ? 1 : 0,
+                           h->o.omega);
             shifted = true;
             zero_in = false;
             std::swap(cur, alt);
@@ -674,7 +678,8 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
         const double sweep_bytes = 2.0 * (3.0 * d.ncell() + d.nfaces()) * sizeof(T) -
                                    (zero_init ? (double)d.ncell() * sizeof(T) : 0.0);
         Prof pf(h, l == 0 ? MG_K_SMOOTH_FINE : MG_K_SMOOTH, sweep_bytes + restrict_bytes);
-        fused_sweep_restrict<T>(s, rtile, H.L[l], cur, alt, H.rhs[l], shift_sum, zero_init ? 1 : 0, H.rhs[l + 1]);
+        fused_sweep_restrict<T>(s, rtile, H.L[l], cur, alt, H.rhs[l], shift_sum, zero_init ? 1 : 0, H.rhs[l + 1],
+                                h->o.omega);
         std::swap(cur, alt);
     } else if (h->o.restrict64) {
         // residual stored in the (free) ping-pong buffer, then the 64-point restriction

@@ -80,6 +80,18 @@ __device__ __forceinline__ float quot(float num, float d) {
 }
 __device__ __forceinline__ double quot(double num, double d) { return num / d; }
 
+// Successive over-relaxation of a Gauss-Seidel value g (feature 5): the cell
+// moves omega times the Gauss-Seidel step from its current value c[oc].  The
+// reference kernel forms the same expression, so both agree bit for bit.
+// Without SOR (omega = 1) this is g itself, compiled without the extra read.
+template <bool SOR, class T>
+__device__ __forceinline__ T sor(T g, const T* c, int oc, T omega) {
+    if constexpr (SOR)
+        return fma(omega, g - c[oc], c[oc]);
+    else
+        return g;
+}
+
 // Residual b - (s - d p) of one cell from its neighbour sum s and diagonal d,
 // with the product taken in a fused multiply-add in every kernel that forms it
 // (so all of them agree bit for bit).
@@ -697,11 +709,11 @@ struct Vec2<double> {
 // With zero_in set, the iterate entering the pass is zero and pin is not read:
 // its loads go through a buffer resource of range 0, which returns 0 (a
 // coarse-grid correction's first smoothing pass; no separate fill).
-template <class T, int TX, int TY, int NSW, bool RES = false>
+template <class T, int TX, int TY, int NSW, bool RES = false, bool SOR = false>
 __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES ? 2 : 0)))
     k_rb_sweep(Lvl<T> L, const T* __restrict__ pin, T* __restrict__ pout, const T* __restrict__ b, int c0, int kc,
                int tiles_x, int tiles_y, const double* __restrict__ shift_sum, double n_cells, int zero_in,
-               T* __restrict__ rc) {
+               T* __restrict__ rc, T omega) {
     using V = typename Vec2<T>::type;
     constexpr int R = 2 * NSW;                  // number of colour stages
     constexpr int E = RES ? 1 : 0;              // extra ring for the residual's neighbours
@@ -899,7 +911,7 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
                 const T* c = sp + sz * PL;
                 const T s = stencil_sum(w0, w1, w2, w3, w4, w5, c[ol], c[orr], c[oc - W], c[oc + W],
                                         sp[sd * PL + oc], sp[su * PL + oc]);
-                const T vnew = quot(s - bb, stencil_diag(w0, w1, w2, w3, w4, w5));
+                const T vnew = sor<SOR>(quot(s - bb, stencil_diag(w0, w1, w2, w3, w4, w5)), c, oc, omega);
                 if constexpr (h < R) {
                     if (in_z && dist <= rg) sp[sz * PL + oc] = vnew;
                     lds_barrier();
@@ -980,7 +992,7 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
                     const T* c = sp + sz * PL;
                     const T s = stencil_sum(w0, w1, w2, w3, w4, w5, c[ol], c[orr], c[oc - W], c[oc + W],
                                             sp[sd * PL + oc], sp[su * PL + oc]);
-                    const T vnew = quot(s - bb, stencil_diag(w0, w1, w2, w3, w4, w5));
+                    const T vnew = sor<SOR>(quot(s - bb, stencil_diag(w0, w1, w2, w3, w4, w5)), c, oc, omega);
                     if constexpr (h < R) {
                         if (in_z && dist <= rg) sp[sz * PL + oc] = vnew;
                         lds_barrier();

@@ -75,9 +75,23 @@ def test_variant_options_are_validated():
         with pytest.raises(mg.MGError) as ei:
             mg.Solver(bx, by, bz, **kw)
         assert ei.value.status == mg.MG_E_INVALID, kw
-    S = mg.Solver(bx, by, bz, omega=1.2)
+    S = mg.Solver(bx, by, bz, restrict64=True)
     assert S.tiles()[:-1] == [-1] * (len(S.levels()) - 1)
     S.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_fused_sor_tiles_bit_identical_to_reference(precision):
+    """The fused red-black passes with over-relaxation (every tile shape, one or
+    two sweeps per pass, the pre-smoothing pass that restricts, zero-input first
+    passes) give exactly the reference one-colour SOR kernels' iterates."""
+    from paper_1410_8568_amd import mg
+    P = ragged_problem((64, 48, 40), seed=5)
+    ref_p, ref_st = gpu_solve(P, precision=precision, tol=1e-10, tile=-1, omega=1.3)
+    for tile in range(1, mg.MG_NUM_TILES + 1):
+        p, st = gpu_solve(P, precision=precision, tol=1e-10, tile=tile, omega=1.3)
+        assert st["history"] == ref_st["history"], tile
+        assert np.array_equal(p, ref_p), tile
 
 
 def test_variants_config1_full_size_matches_oracle():
