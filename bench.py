@@ -498,6 +498,8 @@ def main():
                     help="also time the projection step around the solve (divergence, solve, correction)")
     ap.add_argument("--krylov", type=int, default=1,
                     help="also time the FP64 Krylov solve (flexible CG preconditioned by one V-cycle)")
+    ap.add_argument("--sor-omega", type=float, default=1.2,
+                    help="also time the FP32-refined solve with this SOR factor (1: skip)")
     ap.add_argument("--sweep", action="store_true",
                     help="density-ratio sweep (1e1..1e5, arithmetic and harmonic faces) of the three solvers")
     ap.add_argument("--variants", action="store_true",
@@ -569,12 +571,12 @@ def main():
     torch.cuda.synchronize()
     N = args.n ** 3
 
-    def build(precision, profile=False, krylov="none"):
+    def build(precision, profile=False, krylov="none", omega=1.0):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         kw = {"inner_m": args.inner_m} if args.inner_m else {}
         S = mg.Solver(bx, by, bz, precision=precision, n_coarsest=args.n_coarsest, profile=profile,
-                      graph=args.graph and not profile, krylov=krylov, **kw)
+                      graph=args.graph and not profile, krylov=krylov, omega=omega, **kw)
         torch.cuda.synchronize()
         return S, (time.perf_counter() - t0) * 1e3
 
@@ -606,6 +608,17 @@ def main():
         bytes64 = sum(prof64["kernel_bytes"].values())
         res["fp64_gbps_per_vcycle"] = bytes64 / cyc64 / 1e6 / (ms64 / cyc64)
         res["fp64_cell_updates_per_s"] = N * cyc64 / (ms64 * 1e-3)
+    if args.sor_omega != 1.0:
+        # the same FP32-refined solve with over-relaxed smoothing (the paper's red-black SOR)
+        SS, _ = build("fp32_refined", omega=args.sor_omega)
+        mss, _, sts = timed_solves(SS, b, p, args.steps, args.warmup, args.tol)
+        SS.close()
+        lasts = sts[-1]
+        res["fp32_refined_sor"] = {"omega": args.sor_omega, "ms_per_solve": mss, "cycles": lasts["cycles"],
+                                   "outer": lasts["outer"], "final_rel_residual": lasts["rel_residual"]}
+        if "fp64_ms_per_solve" in res:
+            res["fp32_refined_sor"]["speedup_vs_fp64_mg"] = res["fp64_ms_per_solve"] / mss
+        log(f"fp32_refined omega {args.sor_omega}: {mss:.2f} ms/solve, cycles {lasts['cycles']}")
     if args.krylov:
         # FP64 flexible CG preconditioned by one V-cycle per iteration
         SK, setupk = build("fp64", krylov="fcg")
