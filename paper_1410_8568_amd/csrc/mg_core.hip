@@ -177,6 +177,8 @@ mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
         zgrid((L->d[l].nx + 1) / 2, L->d[l].ny, L->d[l].nz, false, &zb);   // cell-pair kernels
         mb = std::max(mb, zb);
     }
+    // the finest-level residual: one workgroup per RES_FLAT_THREADS cell pairs
+    mb = std::max(mb, (int)(((size_t)L->d[0].ncell() / 2 + RES_FLAT_THREADS - 1) / RES_FLAT_THREADS));
     L->max_blocks = mb;
     L->part = take((size_t)2 * mb * 8);
     L->flag = take(64);
@@ -742,7 +744,11 @@ template <int MODE>
 static int launch_resid(hipStream_t s, const Lvl<double>& L, const double* p, const double* b,
                         const double* inv_s, float* r32, double* part, double* r64 = nullptr) {
     int nb = 0;
-    if ((L.nx & 1) == 0) {
+    if ((L.nx & 1) == 0 && ((uintptr_t)p & 15) == 0 && ((uintptr_t)b & 15) == 0) {
+        const uint32_t units = (uint32_t)((size_t)L.nx * L.ny * L.nz / 2);
+        nb = (int)((units + RES_FLAT_THREADS - 1) / RES_FLAT_THREADS);
+        k_resid_flat<MODE><<<nb, RES_FLAT_THREADS, 0, s>>>(L, p, b, units, inv_s, r32, part, r64);
+    } else if ((L.nx & 1) == 0 && ((uintptr_t)p & 15) == 0) {
         const ColGrid G = zgrid(L.nx / 2, L.ny, L.nz, false, &nb);
         k_resid_cells<double, 2, MODE><<<nb, CBX * CBY, 0, s>>>(L, p, b, G, inv_s, r32, part, r64);
     } else {
