@@ -219,8 +219,8 @@ def write_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, gib=1):
     WRITE_SIZE over the bench, and over --calibrate-copy.  The counters (KiB per
     dispatch) are scaled by what they read for the plain copy of known size.  The
     kernel class is the FP32 fine-grid smoother: among the k_rb_sweep<float, ...>
-    dispatches of the solves (from the first residual pass on; the setup's
-    tuning runs come before), every dispatch whose fetch is at least 40% of the
+    dispatches of the solves (from the first finest-level residual pass on; the
+    setup's tuning runs come before), every dispatch whose fetch is at least 40% of the
     largest (the finest level; the next level moves 8x less), fused-restriction
     and plain passes alike, as the bench's roofline averages over both.  Dispatches of the two runs are
     paired by their order within each (kernel, grid) group."""
@@ -237,7 +237,8 @@ def write_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, gib=1):
     def groups(d):
         # dispatches from the first solve on (the setup's smoother tuning comes before it)
         rows = sorted(_counter_rows(d), key=lambda r: int(r["Dispatch_Id"]))
-        first = min(int(r["Dispatch_Id"]) for r in rows if r["Kernel_Name"].startswith("void mgk::k_resid_cells"))
+        first = min(int(r["Dispatch_Id"]) for r in rows
+                    if r["Kernel_Name"].startswith(("void mgk::k_resid_flat", "void mgk::k_resid_cells")))
         g = {}
         for r in rows:
             if int(r["Dispatch_Id"]) >= first and r["Kernel_Name"].startswith("void mgk::k_rb_sweep<float"):
