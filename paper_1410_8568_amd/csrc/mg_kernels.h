@@ -1525,6 +1525,33 @@ __global__ void k_refine_update(double* __restrict__ p, const float* __restrict_
         p[t] = (p[t] - c) + s * (double)e[t];
 }
 
+// The same update, one thread per value pair (n even, p 16-byte aligned), 512
+// threads per workgroup: the streaming form that measured fastest here.
+__global__ void __launch_bounds__(512) k_refine_update2(double* __restrict__ p, const float* __restrict__ e,
+                                                        const double* __restrict__ scal_s, size_t n,
+                                                        const double* __restrict__ shift_sum) {
+    const size_t t = (size_t)blockIdx.x * 512 + threadIdx.x;
+    if (2 * t >= n) return;
+    const double c = shift_sum[0] / (double)n;
+    const double s = scal_s[0];
+    double2 v = *reinterpret_cast<const double2*>(p + 2 * t);
+    const float2 w = *reinterpret_cast<const float2*>(e + 2 * t);
+    v.x = (v.x - c) + s * (double)w.x;
+    v.y = (v.y - c) + s * (double)w.y;
+    *reinterpret_cast<double2*>(p + 2 * t) = v;
+}
+
+// p -= sum/n for n values (n even, p 16-byte aligned), one thread per pair.
+__global__ void __launch_bounds__(512) k_sub_mean2(double* __restrict__ p, const double* __restrict__ sum, size_t n) {
+    const size_t t = (size_t)blockIdx.x * 512 + threadIdx.x;
+    if (2 * t >= n) return;
+    const double mean = sum[0] / (double)n;
+    double2 v = *reinterpret_cast<const double2*>(p + 2 * t);
+    v.x = v.x - mean;
+    v.y = v.y - mean;
+    *reinterpret_cast<double2*>(p + 2 * t) = v;
+}
+
 // ---------------------------------------------------------------- Krylov acceleration
 //
 // Flexible conjugate gradients on A = -L, preconditioned by one V-cycle from a
