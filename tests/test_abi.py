@@ -59,3 +59,57 @@ def test_status_strings_and_null_handles():
     L.mg_destroy(None)
     L.mg_server_destroy(None)
     assert L.mg_default_options(None) == mg.MG_E_INVALID
+
+
+def test_new_option_validation_on_the_host():
+    """Krylov and cycle-variant options are checked by the workspace planner
+    (no device call)."""
+    from paper_1410_8568_amd import mg
+    n = (32, 32, 32)
+    base = mg.workspace_bytes(n, mg.options())
+    # the Krylov solve keeps four more FP64 vectors on the finest level
+    assert mg.workspace_bytes(n, mg.options(krylov="fcg")) - base >= 32 * 32 ** 3
+    for kw in (dict(precision="fp32_refined", krylov="fcg"), dict(omega=0.0), dict(omega=2.0),
+               dict(coarse_gmres=mg_max_m() + 1), dict(coarse_gmres=-1), dict(coarse_gmres=4, coarse_gmres_tol=0.0),
+               dict(coarse_gmres=4, coarse_gmres_maxit=0)):
+        with pytest.raises(mg.MGError) as ei:
+            mg.workspace_bytes(n, mg.options(**kw))
+        assert ei.value.status == mg.MG_E_INVALID, kw
+    o = mg.options()
+    o.krylov = 2
+    with pytest.raises(mg.MGError):
+        mg.workspace_bytes(n, o)
+    for kw in (dict(omega=1.3), dict(restrict64=True), dict(coarse_gmres=16), dict(krylov="fcg", omega=1.2)):
+        assert mg.workspace_bytes(n, mg.options(**kw)) > 0
+
+
+def mg_max_m():
+    import re
+    src = open(os.path.join(ROOT, "include", "mg.h")).read()
+    return int(re.search(r"#define MG_GMRES_MAX_M (\d+)", src).group(1))
+
+
+def test_new_entry_points_reject_bad_arguments_without_a_device():
+    from paper_1410_8568_amd import mg
+    L = mg.lib()
+    d = ctypes.c_double
+    g = mg.Grid(4, 4, 4)
+    assert L.mg_divergence(None, None, None, None, d(1.0), None, None) == mg.MG_E_INVALID
+    assert L.mg_divergence(ctypes.byref(mg.Grid(-1, 4, 4)), None, None, None, d(1.0), None, None) == mg.MG_E_INVALID
+    # an empty grid is a no-op (nothing is launched, no array is touched)
+    assert L.mg_divergence(ctypes.byref(mg.Grid(0, 4, 4)), None, None, None, d(1.0), None, None) == mg.MG_OK
+    assert L.mg_correct_velocity(None, None, d(1.0), None, None, None, None) == mg.MG_E_INVALID
+    assert L.mg_project(None, None, None, None, d(0.1), d(0.1), None, None, d(1e-10), None, None) == mg.MG_E_INVALID
+    assert L.mg_faces_from_levelset(None, None, d(1.0), d(1.0), d(0.1), 0, None, None, None, None) == mg.MG_E_INVALID
+    fake = ctypes.c_void_p(256)   # never dereferenced: the arguments are rejected first
+    for rho_l, rho_g, eps, harm in ((0.0, 1.0, 0.1, 0), (1.0, -1.0, 0.1, 0), (1.0, 1.0, 0.0, 0), (1.0, 1.0, 0.1, 2)):
+        assert L.mg_faces_from_levelset(ctypes.byref(g), fake, d(rho_l), d(rho_g), d(eps), harm, fake, fake, fake,
+                                        None) == mg.MG_E_INVALID
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
