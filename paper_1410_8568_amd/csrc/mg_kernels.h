@@ -614,49 +614,40 @@ __device__ __forceinline__ void lds_barrier() {
 // registers plus a per-lane 32-bit byte offset, so a load costs no per-lane
 // address arithmetic and no 64-bit address registers.  The format word is the
 // gfx9-family one for untyped 32-bit elements; the range is the maximum unless
-// stated (every access here is in bounds by construction).
-typedef int i32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-__device__ float buf_ld_f32(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.f32");
-__device__ f32x2 buf_ld_f32x2(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.v2f32");
-__device__ double buf_ld_f64(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.f64");
-__device__ f64x2 buf_ld_f64x2(i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.load.v2f64");
-__device__ void buf_st_f32x2(f32x2 v, i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.store.v2f32");
-__device__ void buf_st_f64x2(f64x2 v, i32x4 rsrc, int voff, int soff, int aux) __asm("llvm.amdgcn.raw.buffer.store.v2f64");
+// stated (every access here is in bounds by construction).  The resource is
+// built with the compiler's own resource builtin, whose result it keeps in
+// scalar registers: a resource assembled as a plain integer vector could be
+// placed in vector registers, and every access through it then becomes a loop
+// over the distinct values of the wavefront.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // range: bytes addressable from p; loads at or past it return 0 without
 // touching memory (used with range 0 to read an all-zero operand).
-__device__ __forceinline__ i32x4 buf_rsrc(const void* p, int range = -1) {
+__device__ __forceinline__ Rsrc buf_rsrc(const void* p, int range = -1) {
     const uint64_t a = (uint64_t)p;
-    i32x4 r;
-    r.x = __builtin_amdgcn_readfirstlane((int)(uint32_t)a);
-    r.y = __builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));   // stride 0
-    r.z = range;
-    r.w = 0x00020000;
-    return r;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a), hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), (short)0,
+                                             __builtin_amdgcn_readfirstlane(range), 0x00020000);
 }
-__device__ __forceinline__ float2 buf_ld2(i32x4 r, uint32_t off, const float*) {
-    const f32x2 v = buf_ld_f32x2(r, (int)off, 0, 0);
-    return make_float2(v.x, v.y);
+__device__ __forceinline__ float2 buf_ld2(Rsrc r, uint32_t off, const float*) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
-__device__ __forceinline__ double2 buf_ld2(i32x4 r, uint32_t off, const double*) {
-    const f64x2 v = buf_ld_f64x2(r, (int)off, 0, 0);
-    return make_double2(v.x, v.y);
+__device__ __forceinline__ double2 buf_ld2(Rsrc r, uint32_t off, const double*) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
 }
-__device__ __forceinline__ float buf_ld1(i32x4 r, uint32_t off, const float*) { return buf_ld_f32(r, (int)off, 0, 0); }
-__device__ __forceinline__ double buf_ld1(i32x4 r, uint32_t off, const double*) { return buf_ld_f64(r, (int)off, 0, 0); }
-__device__ __forceinline__ void buf_st2(float2 v, i32x4 r, uint32_t off) {
-    f32x2 w;
-    w.x = v.x;
-    w.y = v.y;
-    buf_st_f32x2(w, r, (int)off, 0, 0);
+__device__ __forceinline__ float buf_ld1(Rsrc r, uint32_t off, const float*) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
 }
-__device__ __forceinline__ void buf_st2(double2 v, i32x4 r, uint32_t off) {
-    f64x2 w;
-    w.x = v.x;
-    w.y = v.y;
-    buf_st_f64x2(w, r, (int)off, 0, 0);
+__device__ __forceinline__ double buf_ld1(Rsrc r, uint32_t off, const double*) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buf_st2(float2 v, Rsrc r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_st2(double2 v, Rsrc r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)off, 0, 0);
 }
 
 // Compile-time loop: f(std::integral_constant<int, i>) for i = B .. E-1, so that
@@ -720,7 +711,10 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
     constexpr int RXs = R + 2 * E, RYs = R + E; // staged ring (x: whole pairs)
     constexpr int W = TX + 2 * RXs, H = TY + 2 * RYs, W2 = W / 2;
     constexpr int PW = TX / 2 + R, PH = TY + 2 * (R - 1 + E), NT = PW * PH;
-    constexpr int NS = R + 3 + E;               // plane slots: R + 2 (+1) live, one being refilled
+    // plane slots: R + 2 (+1) live, one being refilled; FP32 rounds up to 8 so
+    // that a slot index is a mask, not a division (one more plane of LDS)
+    constexpr int NS = sizeof(T) == 4 ? 8 : R + 3 + E;
+    static_assert(NS >= R + 3 + E, "too few plane slots");
     static_assert(!RES || (TX % 2 == 0 && TY % 2 == 0), "restriction needs even tiles");
     constexpr int PL = H * W;                   // elements of a staged plane
     constexpr int NV = H * W2;                  // pairs in a staged plane
@@ -762,7 +756,7 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
     auto kclamp = [&](int k) { return k < 0 ? 0 : (k >= nz ? nz - 1 : k); };
     const int pin_range = zero_in ? 0 : -1;   // zero_in: every load of pin returns 0
     auto fetch_ring = [&](int k, V* v) {
-        const i32x4 r = buf_rsrc(pin + (size_t)kclamp(k) * plane, pin_range);
+        const Rsrc r = buf_rsrc(pin + (size_t)kclamp(k) * plane, pin_range);
 #pragma unroll
         for (int u = 0; u < NP; u++) v[u] = buf_ld2(r, roff[u], tag);
     };
@@ -794,7 +788,7 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
     asm volatile("" : "+v"(cbx), "+v"(cby));
     auto fetch_fb = [&](int k, FB& f) {
         const size_t pk = (size_t)kclamp(k) * plane;
-        const i32x4 rx = buf_rsrc(L.fx + pk), ry = buf_rsrc(L.fy + pk);
+        const Rsrc rx = buf_rsrc(L.fx + pk), ry = buf_rsrc(L.fy + pk);
         f.fx = buf_ld2(rx, cb, tag);
         f.fxu = buf_ld1(rx, cbx, tag);
         f.fy = buf_ld2(ry, cb, tag);
@@ -827,7 +821,7 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
         constexpr int NQ = R + 1 + 2 * E;   // RES keeps two more planes for the residual
         FB fq[NQ];        // fq[h]: x/y faces and b of plane t - h + 1 during step t (fq[0] in flight)
         V fzq[NQ + 1];    // fzq[h]: z-faces of plane t - h + 2 during step t (fzq[0] in flight)
-        auto lslot = [&](int k) { return (k - tfirst + NS) % NS; };
+        auto lslot = [&](int k) { return (int)((unsigned)(k - tfirst + NS) % (unsigned)NS); };   // k >= tfirst - 1
         fetch_ring(tfirst - 1, ring);
         store_ring(lslot(tfirst - 1), tfirst - 1, ring);
         fetch_ring(tfirst, ring);
