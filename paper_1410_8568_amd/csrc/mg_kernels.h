@@ -816,35 +816,41 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
 
     V ring[NP];
     if constexpr (sizeof(T) == 4 || NSW == 1 || RES) {
-        // One step per iteration; the register queues shift by one plane per
-        // step (fewer live registers, so more waves fit per CU).
+        // The register queues shift with the planes.  U steps per iteration:
+        // step j of an iteration reads its queues at offset A = U - 1 - j and the
+        // queues shift by U at the end, so every entry moves once per U steps.
+        // U = 2 in FP32 two-sweep passes without the residual (one more queue
+        // entry fits their registers without costing waves), else 1.
+        constexpr int U = (sizeof(T) == 4 && NSW == 2 && !RES) ? 2 : 1;
         constexpr int NQ = R + 1 + 2 * E;   // RES keeps two more planes for the residual
-        FB fq[NQ];        // fq[h]: x/y faces and b of plane t - h + 1 during step t (fq[0] in flight)
-        V fzq[NQ + 1];    // fzq[h]: z-faces of plane t - h + 2 during step t (fzq[0] in flight)
+        constexpr int NZ = R + 2 + 2 * E;
+        FB fq[NQ + U - 1];   // fq[h + A]: x/y faces and b of plane t - h + 1 during step t (fq[A] in flight)
+        V fzq[NZ + U - 1];   // fzq[h + A]: z-faces of plane t - h + 2 during step t (fzq[A] in flight)
         auto lslot = [&](int k) { return (int)((unsigned)(k - tfirst + NS) % (unsigned)NS); };   // k >= tfirst - 1
         fetch_ring(tfirst - 1, ring);
         store_ring(lslot(tfirst - 1), tfirst - 1, ring);
         fetch_ring(tfirst, ring);
         store_ring(lslot(tfirst), tfirst, ring);
         fetch_ring(tfirst + 1, ring);
-        fetch_fb(tfirst, fq[0]);
-        fzq[0] = fetch_fz(tfirst + 1);
-        fzq[1] = fetch_fz(tfirst);
-        static_for<1, NQ>([&](auto sc) { fq[decltype(sc)::value] = fq[0]; });
-        static_for<2, NQ + 1>([&](auto sc) { fzq[decltype(sc)::value] = fzq[1]; });
+        fetch_fb(tfirst, fq[U]);
+        fzq[U] = fetch_fz(tfirst + 1);
+        fzq[U + 1] = fetch_fz(tfirst);
+        static_for<U + 1, NQ + U - 1>([&](auto sc) { fq[decltype(sc)::value] = fq[U]; });
+        static_for<U + 2, NZ + U - 1>([&](auto sc) { fzq[decltype(sc)::value] = fzq[U + 1]; });
         // RES: residual r = b - (s - d p) of the tile's cells on plane t - R - 1 (whose
         // neighbours are final), summed over the x pair, then over the plane pair;
         // the row pair is added through LDS one step later.
         __shared__ T red[RES ? PH : 1][RES ? PW : 1];
         const bool tpair = RES && dist0 == 0 && dist1 == 0;   // a pair of the tile
         T racc = T(0);
-        auto epilogue = [&](int zr) {
+        auto epilogue = [&](int zr, auto ac) {
             if constexpr (RES) {
+                constexpr int A = decltype(ac)::value;
                 if (zr - 1 >= k0 && ((zr - 1) & 1) && tpair && !(gj & 1))
                     rc[cidx(ia >> 1, gj >> 1, (zr - 1) >> 1, nx >> 1, ny >> 1)] = T(0.5) * (racc + red[lj + 1][q]);
                 if (zr >= k0 && zr < k1 && tpair) {
-                    const FB& f = fq[R + 2];
-                    const V wz0 = fzq[R + 3], wz1 = fzq[R + 2];
+                    const FB& f = fq[R + 2 + A];
+                    const V wz0 = fzq[R + 3 + A], wz1 = fzq[R + 2 + A];
                     const T* c = sp + lslot(zr) * PL;
                     const T* cd = sp + lslot(zr - 1) * PL;
                     const T* cu = sp + lslot(zr + 1) * PL;
@@ -865,23 +871,16 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
                 }
             }
         };
-        for (int t = tfirst; t <= tlast + E; t++) {
-            static_for<0, NQ - 1>([&](auto hc) {
-                constexpr int h = NQ - 1 - decltype(hc)::value;
-                fq[h] = fq[h - 1];
-            });
-            static_for<0, NQ>([&](auto hc) {
-                constexpr int h = NQ - decltype(hc)::value;
-                fzq[h] = fzq[h - 1];
-            });
+        auto step = [&](int t, auto ac) {
+            constexpr int A = decltype(ac)::value;
             store_ring(lslot(t + 1), t + 1, ring);
-            mask_fb(fq[1]);
-            mask_fz(t + 1, fzq[1]);
+            mask_fb(fq[1 + A]);
+            mask_fz(t + 1, fzq[1 + A]);
             lds_barrier();
             fetch_ring(t + 2, ring);                  // in flight during this step
-            fetch_fb(t + 1, fq[0]);
-            fzq[0] = fetch_fz(t + 2);
-            epilogue(t - R - 1);
+            fetch_fb(t + 1, fq[A]);
+            fzq[A] = fetch_fz(t + 2);
+            epilogue(t - R - 1, ac);
             const int e = (c0 + i0 + gj + t) & 1;
             const int dist = e ? dist1 : dist0;
             const int oc = (2 * row + e) * W2 + qq;                   // the cell
@@ -894,13 +893,13 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
                 const int z = t - h + 1;
                 const int sz = lslot(z), sd = lslot(z - 1), su = lslot(z + 1);
                 const bool in_z = z >= 0 && z < nz && z >= k0 - rg && z < k1 + rg;
-                const FB& f = fq[h];
+                const FB& f = fq[h + A];
                 const T w0 = e ? f.fx.y : f.fx.x;
                 const T w1 = e ? f.fxu : f.fx.y;
                 const T w2 = e ? f.fy.y : f.fy.x;
                 const T w3 = e ? f.fyu.y : f.fyu.x;
-                const T w4 = e ? fzq[h + 1].y : fzq[h + 1].x;
-                const T w5 = e ? fzq[h].y : fzq[h].x;
+                const T w4 = e ? fzq[h + 1 + A].y : fzq[h + 1 + A].x;
+                const T w5 = e ? fzq[h + A].y : fzq[h + A].x;
                 const T bb = e ? f.bb.y : f.bb.x;
                 const T* c = sp + sz * PL;
                 const T s = stencil_sum(w0, w1, w2, w3, w4, w5, c[ol], c[orr], c[oc - W], c[oc + W],
@@ -922,11 +921,26 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
                     }
                 }
             });
+        };
+        const int tend = tlast + E;
+        for (int t = tfirst; t <= tend; t += U) {
+            step(t, std::integral_constant<int, U - 1>{});
+            if constexpr (U == 2) {
+                if (t + 1 <= tend) step(t + 1, std::integral_constant<int, 0>{});
+            }
+            static_for<0, NQ - 1>([&](auto hc) {   // shift by U
+                constexpr int h = NQ + U - 2 - decltype(hc)::value;
+                fq[h] = fq[h - U];
+            });
+            static_for<0, NZ - 1>([&](auto hc) {
+                constexpr int h = NZ + U - 2 - decltype(hc)::value;
+                fzq[h] = fzq[h - U];
+            });
         }
         if constexpr (RES) {
             // the row pairs of the last (odd) plane of the chunk
             lds_barrier();
-            epilogue(tlast + E - R);
+            epilogue(tlast + E - R, std::integral_constant<int, 0>{});
         }
     } else {
         // FP64, several sweeps: the loop is unrolled by NS steps, so every queue
