@@ -181,14 +181,15 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None
-    if there is none or the kernel sources changed since it was taken."""
+def traffic_for(kernel, n):
+    """HBM bytes per launch of `kernel` on the n^3 workload from the committed
+    counter summary, or None if there is none for that workload or the kernel
+    sources changed since it was taken."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except Exception:
         return None
-    if t.get("source_sha") != kernel_source_sha() or t.get("class") != kernel:
+    if t.get("source_sha") != kernel_source_sha() or t.get("class") != kernel or t.get("n") != n:
         return None
     return t.get("bytes_per_launch")
 
@@ -214,7 +215,7 @@ def _counter_rows(d):
     return rows
 
 
-def write_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, gib=1):
+def write_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, n, gib=1):
     """profiles/traffic.json from four rocprofv3 --pmc runs: FETCH_SIZE and
     WRITE_SIZE over the bench, and over --calibrate-copy.  The counters (KiB per
     dispatch) are scaled by what they read for the plain copy of known size.  The
@@ -223,7 +224,8 @@ def write_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, gib=1):
     setup's tuning runs come before), every dispatch whose fetch is at least 40% of the
     largest (the finest level; the next level moves 8x less), fused-restriction
     and plain passes alike, as the bench's roofline averages over both.  Dispatches of the two runs are
-    paired by their order within each (kernel, grid) group."""
+    paired by their order within each (kernel, grid) group.  n: the grid size of
+    the bench run the counters were taken on."""
     copy_bytes = gib * (1 << 30)
 
     def copy_kib(d):
@@ -255,7 +257,7 @@ def write_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, gib=1):
                 fetch.append(f * 1024.0 * fs)
                 write.append(wv[i] * 1024.0 * ws)
                 kernels.add(k[0].replace("void mgk::", ""))
-    out = {"class": "smooth_fine", "kernels": sorted(kernels), "dispatches": len(fetch),
+    out = {"class": "smooth_fine", "n": n, "kernels": sorted(kernels), "dispatches": len(fetch),
            "fetch_bytes": sum(fetch) / len(fetch), "write_bytes": sum(write) / len(write),
            "bytes_per_launch": (sum(fetch) + sum(write)) / len(fetch), "fetch_scale": fs, "write_scale": ws,
            "source_sha": kernel_source_sha()}
@@ -520,7 +522,7 @@ def main():
     ap.add_argument("--slots", type=int, default=16)
     args = ap.parse_args()
     if args.traffic:
-        write_traffic(*args.traffic)
+        write_traffic(*args.traffic, n=args.n)
         return
     if args.summarize:
         summarize(args.summarize)
@@ -682,7 +684,7 @@ def main():
         "gbps_per_vcycle": bytes32 / cyc32 / 1e6 / (ms32 / cyc32),
         "cell_updates_per_s": N * cyc32 / (ms32 * 1e-3),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_for(dom),
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_for(dom, args.n),
                      "avg_launch_ms": dom_avg_ms, "bytes_per_launch": dom_bytes},
         "kernel_ms_fp32_refined": prof32["kernel_ms"],
     }
