@@ -163,11 +163,13 @@ def test_error_paths():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
-@pytest.mark.parametrize("n", [(64, 48, 40), (144, 80, 48)])
+@pytest.mark.parametrize("n", [(64, 48, 40), (144, 80, 48), (16, 16, 36), (16, 16, 52)])
 def test_fused_sweep_tiles_bit_identical(precision, n):
     """The fused red-black sweep (halo recomputed per tile, chunked in z) gives
     exactly the same iterates as the one-colour-per-pass reference kernels, for
-    every tile shape, including ragged tiles and chunks.  This also covers the
+    every tile shape, including ragged tiles and chunks.  nz = 36 and 52 give
+    chunks of 9 planes (and a last one of 7), so a chunk has an odd number of
+    plane steps (the FP32 two-sweep pass runs two steps per iteration).  This also covers the
     zero-input first pass of each coarse correction (the reference fills instead)
     and, in FP32 for the tiles that have it, the pre-smoothing pass that forms and
     restricts the residual itself (the reference restricts in a separate pass)."""
