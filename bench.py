@@ -516,7 +516,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--serve", action="store_true", help="Poisson-arrival serving sweep")
     ap.add_argument("--rates", default="50,100,200,300,400,500")
-    ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--pool", type=int, default=2)
     ap.add_argument("--arena-gb", type=float, default=24.0)
     ap.add_argument("--slots", type=int, default=16)
