@@ -624,7 +624,8 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // range: bytes addressable from p; loads at or past it return 0 without
-// touching memory (used with range 0 to read an all-zero operand).
+// touching memory (used with range 0 to read an all-zero operand).  p and range
+// must be the same in every lane of the wavefront: the resource takes lane 0's.
 __device__ __forceinline__ Rsrc buf_rsrc(const void* p, int range = -1) {
     const uint64_t a = (uint64_t)p;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a), hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
