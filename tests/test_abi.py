@@ -113,3 +113,27 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_bench_traffic_figure_is_tied_to_workload_and_kernel_code(tmp_path, monkeypatch):
+    """The committed HBM-traffic figure is reported only for the grid size and
+    kernel code it was measured on; comments do not count as code."""
+    import json
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    src = tmp_path / "k.h"
+    src.write_text("// a kernel\nint f() { return 1; }   // trailing note\n/* block\n comment */\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", ["k.h"])
+    sha = bench.kernel_source_sha()
+    tf = tmp_path / "traffic.json"
+    tf.write_text(json.dumps({"class": "smooth_fine", "n": 512, "bytes_per_launch": 3.0e9, "source_sha": sha}))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tf))
+    assert bench.traffic_for("smooth_fine", 512) == 3.0e9
+    assert bench.traffic_for("smooth_fine", 1024) is None
+    assert bench.traffic_for("other_kernel", 512) is None
+    src.write_text("// reworded\nint f() { return 1; }\n")
+    assert bench.traffic_for("smooth_fine", 512) == 3.0e9
+    src.write_text("int f() { return 2; }\n")
+    assert bench.traffic_for("smooth_fine", 512) is None
