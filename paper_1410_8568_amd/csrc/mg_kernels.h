@@ -688,8 +688,8 @@ struct Vec2<double> {
 // j = j0-R+1+lj, so every global access is a 2-element vector; at step t all
 // R stages fall on the same cell of the pair (the colour of a column flips
 // from plane to plane).  In LDS the even and odd columns of a row are kept in
-// two half rows, so the lanes of a wave, each touching one cell of its pair,
-// hit consecutive banks.  The face coefficients and right-hand side of the pair
+// two half rows, so the lanes of one row, each touching one cell of its pair,
+// hit consecutive banks (a wave spans two rows, whose accesses may share banks).  The face coefficients and right-hand side of the pair
 // stay in registers while their plane is in flight (the upper z-face of a cell
 // is the lower z-face of the plane above).  Planes of pin and the z-faces are
 // loaded two steps ahead, the other faces and b one step ahead, before the
