@@ -687,9 +687,13 @@ struct Vec2<double> {
 // Thread (q, lj) owns the aligned cell pair i = i0-R+2q, i0-R+1+2q of row
 // j = j0-R+1+lj, so every global access is a 2-element vector; at step t all
 // R stages fall on the same cell of the pair (the colour of a column flips
-// from plane to plane).  In LDS the even and odd columns of a row are kept in
-// two half rows, so the lanes of one row, each touching one cell of its pair,
-// hit consecutive banks (a wave spans two rows, whose accesses may share banks).  The face coefficients and right-hand side of the pair
+// from plane to plane).  In LDS each row of a plane is kept as two half rows.
+// FP32 passes split a row by colour class, so a stage (which updates one class
+// and reads the other) has every lane of a wave in the same class, and the
+// half-row stride is chosen for the thread-row width so that the rows a wave
+// spans fall on consecutive banks; FP64 passes (whose registers are full) split
+// it by column parity, which needs fewer index operations.  The face
+// coefficients and right-hand side of the pair
 // stay in registers while their plane is in flight (the upper z-face of a cell
 // is the lower z-face of the plane above).  Planes of pin and the z-faces are
 // loaded two steps ahead, the other faces and b one step ahead, before the
@@ -712,12 +716,18 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
     constexpr int RXs = R + 2 * E, RYs = R + E; // staged ring (x: whole pairs)
     constexpr int W = TX + 2 * RXs, H = TY + 2 * RYs, W2 = W / 2;
     constexpr int PW = TX / 2 + R, PH = TY + 2 * (R - 1 + E), NT = PW * PH;
+    // Half rows by colour class (CL, FP32) with stride HS, the smallest
+    // PW/2 + 32k >= W2, so two thread rows of PW lanes, 2 HS apart, cover
+    // consecutive banks (64 banks of 4 bytes); else by column parity, stride W2.
+    constexpr bool CL = sizeof(T) == 4;
+    constexpr int HS = CL ? PW / 2 + 32 * ((2 * W2 - PW + 63) / 64) : W2;
+    static_assert(PW % 2 == 0 && HS >= W2, "half-row stride");
     // plane slots: R + 2 (+1) live, one being refilled; FP32 rounds up to 8 so
     // that a slot index is a mask, not a division (one more plane of LDS)
     constexpr int NS = sizeof(T) == 4 ? 8 : R + 3 + E;
     static_assert(NS >= R + 3 + E, "too few plane slots");
     static_assert(!RES || (TX % 2 == 0 && TY % 2 == 0), "restriction needs even tiles");
-    constexpr int PL = H * W;                   // elements of a staged plane
+    constexpr int PL = H * 2 * HS;              // elements of a staged plane
     constexpr int NV = H * W2;                  // pairs in a staged plane
     constexpr int NP = (NV + NT - 1) / NT;      // staged pairs per thread
     __shared__ __align__(16) T sp[NS * PL];
@@ -736,20 +746,24 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
     const T shift = shift_sum ? (T)(shift_sum[0] / n_cells) : T(0);
     const int tfirst = k0 - R + 1 - E, tlast = k1 + R - 2 + E;
 
-    // LDS position of (row r, column c) within a plane: (2r + (c & 1)) * W2 + c / 2.
+    // LDS position of (row r, column c) within a plane: (2r + ((r + c) & 1)) * HS + c / 2
+    // with CL, else (2r + (c & 1)) * HS + c / 2 (staged coordinates: r, c from the
+    // tile's corner minus the ring).
     // Global loads are unconditional (clamped to a valid address) so the compiler
     // can leave them in flight until first use; out-of-grid values are zeroed
     // where they are written to LDS or consumed.  Addresses are a per-plane base
     // (uniform) plus a fixed 32-bit byte offset per thread.
     uint32_t roff[NP];   // byte offset of staged pair u within a plane, clamped
-    int rpos[NP];        // LDS position of its even cell (-1: no pair u for this thread)
+    int rpos[NP];        // LDS position 2 r HS + c / 2 of its row (-1: no pair u for this thread)
+    bool rodd[NP];       // odd row: the even cell is in the second half row
     bool rin[NP];        // inside the grid
 #pragma unroll
     for (int u = 0; u < NP; u++) {
         const int v = tid + u * NT;
         const int vi = v % W2, vj = v / W2;
         const int ii = i0 - RXs + 2 * vi, jj = j0 - RYs + vj;
-        rpos[u] = v < NV ? vj * W + vi : -1;
+        rpos[u] = v < NV ? 2 * vj * HS + vi : -1;
+        rodd[u] = CL && (vj & 1);
         rin[u] = v < NV && ii >= 0 && ii < nx && jj >= 0 && jj < ny;
         roff[u] = rin[u] ? (uint32_t)(jj * nx + ii) * (uint32_t)sizeof(T) : 0u;
     }
@@ -768,8 +782,9 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
         for (int u = 0; u < NP; u++)
             if (rpos[u] >= 0) {
                 const bool ok = kin && rin[u];
-                dst[rpos[u]] = ok ? v[u].x - shift : T(0);
-                dst[rpos[u] + W2] = ok ? v[u].y - shift : T(0);
+                const T ev = ok ? v[u].x - shift : T(0), od = ok ? v[u].y - shift : T(0);
+                dst[rpos[u]] = rodd[u] ? od : ev;
+                dst[rpos[u] + HS] = rodd[u] ? ev : od;
             }
     };
     // x- and y-face coefficients and right-hand side of the pair on one plane (the
@@ -855,12 +870,16 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
                     const T* c = sp + lslot(zr) * PL;
                     const T* cd = sp + lslot(zr - 1) * PL;
                     const T* cu = sp + lslot(zr + 1) * PL;
-                    const int o0 = 2 * row * W2 + qq, o1 = o0 + W2;   // even and odd cell
+                    // even and odd cell; with CL a cell's y-neighbours are in the other
+                    // class's half rows
+                    const int ro = CL ? (row & 1) : 0;
+                    const int o0 = (2 * row + ro) * HS + qq, o1 = (2 * row + 1 - ro) * HS + qq;
+                    const int y0 = CL ? o1 : o0, y1 = CL ? o0 : o1;
                     const T s0 = stencil_sum(f.fx.x, f.fx.y, f.fy.x, f.fyu.x, wz0.x, wz1.x, c[o1 - 1], c[o1],
-                                             c[o0 - W], c[o0 + W], cd[o0], cu[o0]);
+                                             c[y0 - 2 * HS], c[y0 + 2 * HS], cd[o0], cu[o0]);
                     const T d0 = stencil_diag(f.fx.x, f.fx.y, f.fy.x, f.fyu.x, wz0.x, wz1.x);
                     const T s1 = stencil_sum(f.fx.y, f.fxu, f.fy.y, f.fyu.y, wz0.y, wz1.y, c[o0], c[o0 + 1],
-                                             c[o1 - W], c[o1 + W], cd[o1], cu[o1]);
+                                             c[y1 - 2 * HS], c[y1 + 2 * HS], cd[o1], cu[o1]);
                     const T d1 = stencil_diag(f.fx.y, f.fxu, f.fy.y, f.fyu.y, wz0.y, wz1.y);
                     const T sum = resid_val(f.bb.x, s0, d0, c[o0]) + resid_val(f.bb.y, s1, d1, c[o1]);
                     if (zr & 1) {
@@ -884,10 +903,12 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
             epilogue(t - R - 1, ac);
             const int e = (c0 + i0 + gj + t) & 1;
             const int dist = e ? dist1 : dist0;
-            const int oc = (2 * row + e) * W2 + qq;                   // the cell
-            const int ol = e ? 2 * row * W2 + qq : (2 * row + 1) * W2 + qq - 1;
-            const int orr = e ? 2 * row * W2 + qq + 1 : (2 * row + 1) * W2 + qq;
-            const int opart = (2 * row + (e ^ 1)) * W2 + qq;          // its pair partner
+            const int hc = CL ? (e + row) & 1 : e;                    // the cell's half row
+            const int oc = (2 * row + hc) * HS + qq;                  // the cell
+            const int opart = (2 * row + 1 - hc) * HS + qq;           // its pair partner
+            const int ol = e ? opart : opart - 1, orr = e ? opart + 1 : opart;   // x-neighbours
+            const int oy = CL ? opart : oc;
+            const int os = oy - 2 * HS, on = oy + 2 * HS;             // y-neighbours
             static_for<1, R + 1>([&](auto hc) {
                 constexpr int h = decltype(hc)::value;
                 constexpr int rg = R - h + E;                           // this stage's ring width
@@ -903,7 +924,7 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
                 const T w5 = e ? fzq[h + A].y : fzq[h + A].x;
                 const T bb = e ? f.bb.y : f.bb.x;
                 const T* c = sp + sz * PL;
-                const T s = stencil_sum(w0, w1, w2, w3, w4, w5, c[ol], c[orr], c[oc - W], c[oc + W],
+                const T s = stencil_sum(w0, w1, w2, w3, w4, w5, c[ol], c[orr], c[os], c[on],
                                         sp[sd * PL + oc], sp[su * PL + oc]);
                 const T vnew = sor<SOR>(quot(s - bb, stencil_diag(w0, w1, w2, w3, w4, w5)), c, oc, omega);
                 if constexpr (h < R) {
@@ -979,10 +1000,12 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
                 // this step updates the same cell (on its own plane)
                 const int e = (c0 + i0 + gj + t) & 1;
                 const int dist = e ? dist1 : dist0;
-                const int oc = (2 * row + e) * W2 + q;                    // the cell
-                const int ol = e ? 2 * row * W2 + q : (2 * row + 1) * W2 + q - 1;
-                const int orr = e ? 2 * row * W2 + q + 1 : (2 * row + 1) * W2 + q;
-                const int opart = (2 * row + (e ^ 1)) * W2 + q;           // its pair partner
+                const int hc = CL ? (e + row) & 1 : e;                    // the cell's half row
+                const int oc = (2 * row + hc) * HS + q;                   // the cell
+                const int opart = (2 * row + 1 - hc) * HS + q;            // its pair partner
+                const int ol = e ? opart : opart - 1, orr = e ? opart + 1 : opart;   // x-neighbours
+                const int oy = CL ? opart : oc;
+                const int os = oy - 2 * HS, on = oy + 2 * HS;             // y-neighbours
                 static_for<1, R + 1>([&](auto hc) {
                     constexpr int h = decltype(hc)::value;
                     constexpr int sz = (u - h + 1 + 2 * NS) % NS;         // slot of this stage's plane
@@ -999,7 +1022,7 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
                     const T w5 = e ? fzq[su].y : fzq[su].x;
                     const T bb = e ? f.bb.y : f.bb.x;
                     const T* c = sp + sz * PL;
-                    const T s = stencil_sum(w0, w1, w2, w3, w4, w5, c[ol], c[orr], c[oc - W], c[oc + W],
+                    const T s = stencil_sum(w0, w1, w2, w3, w4, w5, c[ol], c[orr], c[os], c[on],
                                             sp[sd * PL + oc], sp[su * PL + oc]);
                     const T vnew = sor<SOR>(quot(s - bb, stencil_diag(w0, w1, w2, w3, w4, w5)), c, oc, omega);
                     if constexpr (h < R) {
