@@ -188,7 +188,7 @@ mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
     if (resid_flat_fits(L->d[0]))
         mb = std::max(mb, (int)(((size_t)L->d[0].ncell() / 2 + RES_FLAT_THREADS - 1) / RES_FLAT_THREADS));
     L->max_blocks = mb;
-    L->part = take((size_t)2 * mb * 8);
+    L->part = take((size_t)2 * (mb + FIN_PARTS) * 8);   // partial pairs, then the first stage's
     L->flag = take(64);
     L->total = off;
     return MG_OK;
@@ -721,10 +721,19 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
     }
 }
 
-// Run partial-sum kernel output through k_finish2 into scal[slot], scal[slot+1].
+// Run partial-sum kernel output through k_finish2 into scal[slot], scal[slot+1]:
+// in one workgroup for a few thousand pairs, else in two stages (the finest-level
+// residual of a 512^3 grid leaves 131072 pairs, 55 us for one workgroup).
 static void finish(mg_handle* h, int nblk, int slot) {
     Prof pf(h, MG_K_OTHER, 16.0 * nblk);
-    k_finish2<<<1, FIN_THREADS, 0, h->stream>>>(h->part, nblk, h->scal + slot);
+    if (nblk > 4 * FIN_THREADS) {
+        const int per = (nblk + FIN_PARTS - 1) / FIN_PARTS, g = (nblk + per - 1) / per;
+        double* p2 = h->part + (size_t)2 * h->L.max_blocks;
+        k_finish2_part<<<g, FIN_THREADS, 0, h->stream>>>(h->part, nblk, per, p2);
+        k_finish2<<<1, FIN_THREADS, 0, h->stream>>>(p2, g, h->scal + slot);
+    } else {
+        k_finish2<<<1, FIN_THREADS, 0, h->stream>>>(h->part, nblk, h->scal + slot);
+    }
 }
 
 static void build_hier(mg_handle* h, double* p, Hier<double>& H64, Hier<float>& H32) {

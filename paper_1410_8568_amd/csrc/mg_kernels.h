@@ -22,6 +22,7 @@ constexpr int BX = 64;   // threads along i (one wavefront)
 constexpr int BY = 4;    // rows per block
 constexpr int RED_THREADS = 256;
 constexpr int FIN_THREADS = 1024;
+constexpr int FIN_PARTS = 256;   // first-stage workgroups of a two-stage final sum
 
 __device__ __forceinline__ size_t cidx(int i, int j, int k, int nx, int ny) {
     return ((size_t)k * ny + j) * nx + i;
@@ -165,6 +166,25 @@ __device__ __forceinline__ void block_partials2(double a, double b, double* __re
 }
 
 // out[q] = sum over blocks of part[2*blk+q] (q = 0,1), fixed order.  One block.
+// First stage of the final sum of many partial pairs: workgroup g adds pairs
+// [g per, min((g + 1) per, nblk)) in a fixed order into out[2g], out[2g + 1]
+// (k_finish2 then adds the workgroups' results), so a large sum is spread over
+// the chip instead of one CU.
+__global__ void __launch_bounds__(FIN_THREADS) k_finish2_part(const double* __restrict__ part, int nblk, int per,
+                                                              double* __restrict__ out) {
+    const int lo = blockIdx.x * per, hi = min(nblk, lo + per);
+    double a = 0, b = 0;
+    for (int t = lo + (int)threadIdx.x; t < hi; t += FIN_THREADS) {
+        a += part[2 * t];
+        b += part[2 * t + 1];
+    }
+    block_sum2<FIN_THREADS>(a, b);
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = a;
+        out[2 * blockIdx.x + 1] = b;
+    }
+}
+
 __global__ void __launch_bounds__(FIN_THREADS) k_finish2(const double* __restrict__ part, int nblk,
                                                          double* __restrict__ out) {
     double a = 0, b = 0;
