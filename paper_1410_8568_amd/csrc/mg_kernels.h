@@ -713,9 +713,9 @@ struct Vec2<double> {
 // half-row stride is chosen for the thread-row width so that the rows a wave
 // spans fall on consecutive banks; FP64 passes (whose registers are full) split
 // it by column parity, which needs fewer index operations.  The face
-// coefficients and right-hand side of the pair
-// stay in registers while their plane is in flight (the upper z-face of a cell
-// is the lower z-face of the plane above).  Planes of pin and the z-faces are
+// coefficients and right-hand side of the pair stay in registers while their
+// plane is in flight (the upper z-face of a cell is the lower z-face of the
+// plane above).  Planes of pin and the z-faces are
 // loaded two steps ahead, the other faces and b one step ahead, before the
 // compute of the current step.  Requires even nx (every smoothed level has one).
 //
