@@ -19,6 +19,8 @@
 //     x = phi/eps, I = 0.5 * ((1 + x) + sin(pi * x) / pi),
 //     alpha = 1 / (rho_g + (rho_l - rho_g) * I),
 //     arithmetic 0.5 * (a + b), harmonic (2 * a * b) / (a + b).
+// Outside the band alpha is the value of that formula at I = 0 or 1, which each
+// thread computes once (most cells then need no division).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -38,18 +40,19 @@ struct Props {
     int harmonic;
 };
 
-__device__ __forceinline__ double cell_alpha(double phi, const Props& q) {
+__device__ __forceinline__ double alpha_of(double ind, const Props& q) {
 #pragma clang fp contract(off)
-    double ind;
-    if (phi <= -q.eps)
-        ind = 0.0;
-    else if (phi >= q.eps)
-        ind = 1.0;
-    else {
-        const double x = phi / q.eps;
-        ind = 0.5 * ((1.0 + x) + sin(M_PI * x) / M_PI);
-    }
     return 1.0 / (q.rho_g + (q.rho_l - q.rho_g) * ind);
+}
+
+// ag, al: alpha_of(0) and alpha_of(1), computed once per thread, so only the
+// cells inside the band pay for a division.
+__device__ __forceinline__ double cell_alpha(double phi, const Props& q, double ag, double al) {
+#pragma clang fp contract(off)
+    if (phi <= -q.eps) return ag;
+    if (phi >= q.eps) return al;
+    const double x = phi / q.eps;
+    return alpha_of(0.5 * ((1.0 + x) + sin(M_PI * x) / M_PI), q);
 }
 
 __device__ __forceinline__ double face_mean(double a, double b, int harmonic) {
@@ -68,12 +71,14 @@ __global__ void __launch_bounds__(PT)
     const uint32_t r = t / ux;
     const int i = (int)(t - r * ux) * NC, j = (int)(r % (uint32_t)ny), k = (int)(r / (uint32_t)ny);
     const size_t plane = (size_t)nx * ny, c = (size_t)r * nx + i;
+    const double ag = alpha_of(0.0, q), al = alpha_of(1.0, q);
+    auto cell_alpha = [&](double v) { return ::cell_alpha(v, q, ag, al); };
     double a[NC];
 #pragma unroll
-    for (int e = 0; e < NC; e++) a[e] = cell_alpha(phi[c + e], q);
+    for (int e = 0; e < NC; e++) a[e] = cell_alpha(phi[c + e]);
     // x-faces: i .. i + NC - 1 (the first is a wall at i = 0), and the upper wall
     const size_t fx = ((size_t)k * ny + j) * (nx + 1) + i;
-    bx[fx] = i > 0 ? face_mean(cell_alpha(phi[c - 1], q), a[0], q.harmonic) : 0.0;
+    bx[fx] = i > 0 ? face_mean(cell_alpha(phi[c - 1]), a[0], q.harmonic) : 0.0;
 #pragma unroll
     for (int e = 1; e < NC; e++) bx[fx + e] = face_mean(a[e - 1], a[e], q.harmonic);
     if (i + NC == nx) bx[fx + NC] = 0.0;
@@ -81,7 +86,7 @@ __global__ void __launch_bounds__(PT)
     const size_t fy = ((size_t)k * (ny + 1) + j) * nx + i;
     double o[NC];
 #pragma unroll
-    for (int e = 0; e < NC; e++) o[e] = j > 0 ? face_mean(cell_alpha(phi[c - nx + e], q), a[e], q.harmonic) : 0.0;
+    for (int e = 0; e < NC; e++) o[e] = j > 0 ? face_mean(cell_alpha(phi[c - nx + e]), a[e], q.harmonic) : 0.0;
     if constexpr (NC == 2) {
         *reinterpret_cast<double2*>(by + fy) = make_double2(o[0], o[1]);
         if (j == ny - 1) *reinterpret_cast<double2*>(by + fy + nx) = make_double2(0.0, 0.0);
@@ -92,7 +97,7 @@ __global__ void __launch_bounds__(PT)
     // z-faces (plane k; walls at k = 0 and k = nz)
 #pragma unroll
     for (int e = 0; e < NC; e++)
-        o[e] = k > 0 ? face_mean(cell_alpha(phi[c - plane + e], q), a[e], q.harmonic) : 0.0;
+        o[e] = k > 0 ? face_mean(cell_alpha(phi[c - plane + e]), a[e], q.harmonic) : 0.0;
     if constexpr (NC == 2) {
         *reinterpret_cast<double2*>(bz + c) = make_double2(o[0], o[1]);
         if (k == nz - 1) *reinterpret_cast<double2*>(bz + c + plane) = make_double2(0.0, 0.0);
