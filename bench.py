@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = ["paper_1410_8568_amd/csrc/mg_kernels.h"]
+KERNEL_SOURCES = ["paper_1410_8568_amd/csrc/mg_kernels.h", "paper_1410_8568_amd/csrc/mg_core.hip"]   # kernels and their launch shapes
 METRIC = "time to 1e-10 residual + HBM GB/s per V-cycle; FP32-refined vs FP64 MG"
 
 

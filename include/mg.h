@@ -117,11 +117,12 @@ typedef struct {
 
 enum { MG_KRYLOV_NONE = 0, MG_KRYLOV_FCG = 1 };
 
-/* Fused sweep variants: variant v uses tile (v-1)/2 of the list 64x8, 128x4,
+/* Fused sweep variants: variant v uses tile (v-1)/3 of the list 64x8, 128x4,
    128x8, 64x16 (one sweep per pass), 64x4, 64x8, 128x8, 64x16 (two sweeps per
-   pass), with a target of about 1024 (v odd) or 4096 (v even) workgroups.  The
-   last two two-sweep tiles exist in FP32 only; in FP64 they run as 64x8. */
-#define MG_NUM_TILES 16
+   pass), with a target of about 256, 1024 or 4096 workgroups for (v-1) mod 3 =
+   0, 1, 2.  The last two two-sweep tiles exist in FP32 only; in FP64 they run
+   as 64x8. */
+#define MG_NUM_TILES 24
 
 /* Kernel classes reported in mg_stats when options.profile is set. */
 enum {

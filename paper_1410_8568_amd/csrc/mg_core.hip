@@ -400,22 +400,29 @@ static void launch_sweep(hipStream_t s, const Lvl<T>& L, const T* pin, T* pout, 
             L, pin, pout, b, c0, kc, gx, gy, shift_sum, (double)L.nx * L.ny * L.nz, zero_in, rc, T(1));
 }
 
-// Sweeps done by one pass of fused variant v (1..MG_NUM_TILES).
-static int sweeps_per_pass(int v) { return v > 8 ? 2 : 1; }
+// Fused variant v (1..MG_NUM_TILES): tile (v - 1) / 3 of the list (four one-sweep
+// tiles, then four two-sweep ones), about 256, 1024 or 4096 workgroups for
+// (v - 1) mod 3 = 0, 1, 2.  256 is one workgroup per CU with a whole column per
+// workgroup (no redundant planes at chunk ends); the larger targets cut the
+// columns into z-chunks for levels with few tiles.
+static int variant_target(int v) { return (v - 1) % 3 == 0 ? 256 : ((v - 1) % 3 == 1 ? 1024 : 4096); }
 
-// Variants 13..16 (two sweeps, 128x8 and 64x16 tiles) need more than 64 KiB of
+// Sweeps done by one pass of fused variant v.
+static int sweeps_per_pass(int v) { return v > 12 ? 2 : 1; }
+
+// Variants 19..24 (two sweeps, 128x8 and 64x16 tiles) need more than 64 KiB of
 // LDS in FP64; there they fall back to the 64x8 two-sweep tile.
 template <class T>
 static bool variant_native(int v) {
-    return sizeof(T) == 4 || v <= 12;
+    return sizeof(T) == 4 || v <= 18;
 }
 
 // Fused sweep variant v in 1..MG_NUM_TILES: one pass doing sweeps_per_pass(v) sweeps.
 template <class T>
 static void fused_sweep(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0,
                         const double* shift_sum = nullptr, int zero_in = 0, double omega = 1.0) {
-    const int target = ((v - 1) & 1) ? 4096 : 1024;
-    switch ((v - 1) >> 1) {
+    const int target = variant_target(v);
+    switch ((v - 1) / 3) {
         case 0: launch_sweep<T, 64, 8, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega); break;
         case 1: launch_sweep<T, 128, 4, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega); break;
         case 2: launch_sweep<T, 128, 8, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega); break;
@@ -442,7 +449,7 @@ static void fused_sweep(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* 
 // threads; an FP64 64x16 pass would not fit its registers).
 template <class T>
 static bool has_restrict_variant(int v) {
-    const int t = (v - 1) >> 1;
+    const int t = (v - 1) / 3;
     return v > 0 && (t == 4 || t == 5 || (sizeof(T) == 4 && t == 7));
 }
 
@@ -452,8 +459,8 @@ static bool has_restrict_variant(int v) {
 template <class T>
 static bool fused_sweep_restrict(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b,
                                  const double* shift_sum, int zero_in, T* rc, double omega = 1.0) {
-    const int target = ((v - 1) & 1) ? 4096 : 1024;
-    switch ((v - 1) >> 1) {
+    const int target = variant_target(v);
+    switch ((v - 1) / 3) {
         case 4: launch_sweep<T, 64, 4, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc, omega); return true;
         case 5: launch_sweep<T, 64, 8, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc, omega); return true;
         case 7:
@@ -515,9 +522,12 @@ void tune_load_locked() {
     char line[256];
     while (fgets(line, sizeof line, f)) {
         int pr, x, y, z, v, rv;
-        if (sscanf(line, "{\"bytes\": %d, \"nx\": %d, \"ny\": %d, \"nz\": %d, \"variant\": %d, \"restrict\": %d}", &pr,
-                   &x, &y, &z, &v, &rv) == 6 &&
-            v >= -1 && v <= MG_NUM_TILES && v != 0 && rv >= 0 && rv <= MG_NUM_TILES)
+        int nt = 0;   // entries written for another variant list are skipped
+        if (sscanf(line,
+                   "{\"bytes\": %d, \"nx\": %d, \"ny\": %d, \"nz\": %d, \"variant\": %d, \"restrict\": %d, "
+                   "\"variants\": %d}",
+                   &pr, &x, &y, &z, &v, &rv, &nt) == 7 &&
+            nt == MG_NUM_TILES && v >= -1 && v <= MG_NUM_TILES && v != 0 && rv >= 0 && rv <= MG_NUM_TILES)
             g_tune[{pr, x, y, z}] = {v, rv};
     }
     fclose(f);
@@ -529,8 +539,8 @@ void tune_store_locked(const std::array<int, 4>& k, int v, int rv) {
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "{\"bytes\": %d, \"nx\": %d, \"ny\": %d, \"nz\": %d, \"variant\": %d, \"restrict\": %d}\n", k[0], k[1],
-            k[2], k[3], v, rv);
+    fprintf(f, "{\"bytes\": %d, \"nx\": %d, \"ny\": %d, \"nz\": %d, \"variant\": %d, \"restrict\": %d, \"variants\": %d}\n",
+            k[0], k[1], k[2], k[3], v, rv, MG_NUM_TILES);
     fclose(f);
 }
 }  // namespace

@@ -21,7 +21,7 @@ MG_BC_NEUMANN = 0
 MG_MAX_LEVELS = 24
 MG_MAX_COARSE_CELLS = 512
 MG_MAX_HISTORY = 256
-MG_NUM_TILES = 16
+MG_NUM_TILES = 24
 KERNEL_CLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "refine", "other", "smooth_fine", "krylov"]
 MG_KRYLOV_NONE, MG_KRYLOV_FCG = 0, 1
 MG_K_COUNT = len(KERNEL_CLASSES)
