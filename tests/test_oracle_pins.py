@@ -144,6 +144,142 @@ def test_prolongation_flux_continuity_1d(oracle_lib):
     assert np.allclose(out, np.broadcast_to(expect, out.shape), rtol=0, atol=1e-14)
 
 
+def _flux_face_values_1d(e1, a1):
+    """Per fine child along one axis: the coarse centre value and the face value of
+    eqs. 13-14 read as flux continuity, a_C (e_f - e_C) = a_N (e_N - e_f), with the
+    neighbour beyond a wall replaced by the cell itself (zero normal derivative)."""
+    cn = len(e1)
+    centre = np.empty(2 * cn)
+    face = np.empty(2 * cn)
+    for I in range(cn):
+        for child, nb in ((2 * I, max(I - 1, 0)), (2 * I + 1, min(I + 1, cn - 1))):
+            centre[child] = e1[I]
+            face[child] = (a1[I] * e1[I] + a1[nb] * e1[nb]) / (a1[I] + a1[nb])
+    return centre, face
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_prolongation_flux_continuity_1d_along_y_and_z(oracle_lib, axis):
+    """The same closed form with coarse error and weights varying along y (axis 1
+    of the [k][j][i] arrays) or along z (axis 0) only, so that the y- and z-corner
+    weights of the prolongation are pinned as well as the x ones."""
+    rng = np.random.default_rng(18 + axis)
+    cn = 5
+    e1 = rng.standard_normal(cn)
+    a1 = rng.uniform(1e-3, 1.0, cn)
+    cshape = [3, 4, 2]
+    cshape[axis] = cn
+    view = [1, 1, 1]
+    view[axis] = cn
+    ec = np.broadcast_to(e1.reshape(view), cshape).copy()
+    a = np.broadcast_to(a1.reshape(view), cshape).copy()
+    out = oracle_lib.prolong_add(a, ec, np.zeros(tuple(2 * s for s in cshape)))
+    centre, face = _flux_face_values_1d(e1, a1)
+    expect = 0.5 * (centre + face)
+    fview = [1, 1, 1]
+    fview[axis] = 2 * cn
+    assert np.allclose(out, np.broadcast_to(expect.reshape(fview), out.shape), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("plane", [(1, 2), (0, 2), (0, 1)])
+def test_prolongation_edge_corner_is_weighted_mean_of_four(oracle_lib, plane):
+    """Data varying in two directions only (the third is constant): a fine value is
+    the mean of four octant corners, the coarse cell, its two face values (the 1-D
+    flux-continuity closed forms along each direction, pinned above) and the edge
+    value, which the 3-D extension of eqs. 13-14 defines as the coefficient-weighted
+    mean of the four coarse cells sharing the edge.  Checked cell by cell with
+    non-uniform weights, in each of the three coordinate planes (axes of the
+    [k][j][i] arrays)."""
+    rng = np.random.default_rng(30 + plane[0] + 2 * plane[1])
+    pa, pb = plane                      # the two varying axes
+    flat = 3 - pa - pb                  # the constant axis
+    na, nb = 4, 3
+    e2 = rng.standard_normal((na, nb))
+    a2 = rng.uniform(1e-3, 1.0, (na, nb))
+    cshape = [0, 0, 0]
+    cshape[pa], cshape[pb], cshape[flat] = na, nb, 2
+    ec = np.moveaxis(np.broadcast_to(e2[:, :, None], (na, nb, 2)), (0, 1, 2), (pa, pb, flat)).copy()
+    a = np.moveaxis(np.broadcast_to(a2[:, :, None], (na, nb, 2)), (0, 1, 2), (pa, pb, flat)).copy()
+    assert ec.shape == tuple(cshape)
+    out = oracle_lib.prolong_add(a, ec, np.zeros(tuple(2 * s for s in cshape)))
+    out2 = np.moveaxis(out, (pa, pb, flat), (0, 1, 2))   # [fine a][fine b][flat]
+    # the constant direction leaves every fine value unchanged along it
+    assert np.array_equal(out2[:, :, 0], out2[:, :, 1])
+    for fa in range(2 * na):
+        for fb in range(2 * nb):
+            I, J = fa // 2, fb // 2
+            sa, sb = (1 if fa & 1 else -1), (1 if fb & 1 else -1)
+            In, Jn = min(max(I + sa, 0), na - 1), min(max(J + sb, 0), nb - 1)
+            # face values from the 1-D closed form along each direction
+            va = (a2[I, J] * e2[I, J] + a2[In, J] * e2[In, J]) / (a2[I, J] + a2[In, J])
+            vb = (a2[I, J] * e2[I, J] + a2[I, Jn] * e2[I, Jn]) / (a2[I, J] + a2[I, Jn])
+            cells = [(I, J), (In, J), (I, Jn), (In, Jn)]
+            edge = sum(a2[c] * e2[c] for c in cells) / sum(a2[c] for c in cells)
+            want = 0.25 * (e2[I, J] + va + vb + edge)
+            assert abs(out2[fa, fb, 0] - want) < 1e-14, (fa, fb, out2[fa, fb, 0], want)
+            # and the edge value read back from the output is that weighted mean
+            assert abs(4.0 * out2[fa, fb, 0] - e2[I, J] - va - vb - edge) < 1e-13
+
+
+@pytest.mark.parametrize("perm", [(0, 2, 1), (1, 0, 2), (2, 1, 0), (1, 2, 0)])
+def test_prolongation_commutes_with_axis_permutations(oracle_lib, perm):
+    """The prolongation treats the three directions alike: permuting the axes of
+    random 3-D coarse data and weights (non-cubic grid) permutes the result.  An
+    index that reads one direction's offset in another breaks this."""
+    rng = np.random.default_rng(40)
+    ec = rng.standard_normal((3, 4, 5))
+    a = rng.uniform(1e-3, 1.0, ec.shape)
+    base = np.zeros(tuple(2 * s for s in ec.shape))
+    out = oracle_lib.prolong_add(a, ec, base)
+    outp = oracle_lib.prolong_add(np.transpose(a, perm), np.transpose(ec, perm), np.transpose(base, perm))
+    assert np.allclose(outp, np.transpose(out, perm), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_prolongation_commutes_with_reflections(oracle_lib, axis):
+    """Mirroring the grid along one axis mirrors the result: the octant on the low
+    side of a coarse cell takes its corners below it, the high octant above, and
+    walls clamp alike at both ends."""
+    rng = np.random.default_rng(41 + axis)
+    ec = rng.standard_normal((4, 3, 5))
+    a = rng.uniform(1e-3, 1.0, ec.shape)
+    base = np.zeros(tuple(2 * s for s in ec.shape))
+    out = oracle_lib.prolong_add(a, ec, base)
+    outf = oracle_lib.prolong_add(np.flip(a, axis), np.flip(ec, axis), base)
+    assert np.allclose(outf, np.flip(out, axis), rtol=0, atol=1e-14)
+
+
+def test_prolongation_node_corner_by_linearity(oracle_lib):
+    """Full 3-D data: with the weights fixed the prolongation is linear in the
+    coarse error, and the coarse unit vector of one interior cell C spreads to the
+    fine cells with exactly the weight shares of the corners that contain C.  Its
+    fine child in octant s gets (1/8)(1 + sum over the 7 non-empty T of
+    a_C / sum_{m in T-set} a_m), the 2^|T| cells of each T-set being C and its
+    neighbours towards s; checked for all 8 children of an interior cell, which
+    involves the node (|T| = 3) corner and all edges."""
+    rng = np.random.default_rng(43)
+    shape = (4, 5, 6)
+    a = rng.uniform(1e-3, 1.0, shape)
+    K, J, I = 2, 2, 3
+    ec = np.zeros(shape)
+    ec[K, J, I] = 1.0
+    out = oracle_lib.prolong_add(a, ec, np.zeros(tuple(2 * s for s in shape)))
+    for ck in (0, 1):
+        for cj in (0, 1):
+            for ci in (0, 1):
+                sz, sy, sx = (1 if ck else -1), (1 if cj else -1), (1 if ci else -1)
+                total = 1.0
+                for T in range(1, 8):
+                    den = 0.0
+                    for d in range(8):
+                        if d & ~T:
+                            continue
+                        den += a[K + (sz if d & 4 else 0), J + (sy if d & 2 else 0), I + (sx if d & 1 else 0)]
+                    total += a[K, J, I] / den
+                got = out[2 * K + ck, 2 * J + cj, 2 * I + ci]
+                assert abs(got - total / 8.0) < 1e-14, (ck, cj, ci, got, total / 8.0)
+
+
 # --------------------------------------------------------------------------- hierarchy
 
 def test_plan_levels(oracle_lib):
