@@ -172,9 +172,14 @@ mg_status mg_default_options(mg_options *o);
 mg_status mg_workspace_bytes(const mg_grid *g, const mg_options *o, size_t *bytes);
 
 /*
- * Build the hierarchy for one coefficient field (setup steps: copy faces with
- * zero walls, coarsen faces level by level, cell weights for the prolongation,
- * dense inverse of the coarsest operator, FP32 copies in refined mode).
+ * Build the hierarchy for one coefficient field of the pressure equation (9),
+ * discretised by eq. (10) with face coefficients such as those of eqs. (11)-(12)
+ * (Sec. 2.3): copy faces with zero walls, coarsen faces level by level on the
+ * power-of-two hierarchy of Sec. 2.3 (coarse face = mean of the 2x2 fine faces it
+ * covers: restriction and prolongation are not tied to each other, feature list of
+ * Sec. 2.3), cell weights for the flux-conserving prolongation of eqs. (13)-(14)
+ * (feature 4), dense inverse of the coarsest operator (the exact limit of the
+ * coarsest-grid GMRES of feature 6), FP32 copies in refined mode.
  * bx, by, bz: device double arrays in the layout above; read on `stream`, the
  * caller may reuse them once the call returns.  ws: caller-owned device
  * workspace of ws_bytes >= mg_workspace_bytes(), 256-byte aligned, which must
@@ -184,17 +189,24 @@ mg_status mg_workspace_bytes(const mg_grid *g, const mg_options *o, size_t *byte
  * interior coefficient found by the device check), MG_E_WORKSPACE, MG_E_HIP.
  */
 mg_status mg_setup(const mg_grid *g, const mg_options *o, const double *bx, const double *by,
-                   const double *bz, int bc, void *ws, size_t ws_bytes, void *stream,
+                   const double *bz, mg_bc bc, void *ws, size_t ws_bytes, void *stream,
                    mg_handle **out);
 
 /*
- * Solve L p = b - mean(b) to relative residual ||b_bar - L p||_2 / ||b_bar||_2 <= tol.
+ * Solve L p = b - mean(b) (eq. 9 in the discrete form of eq. 10, Neumann walls) with
+ * the modified V-cycle of Sec. 2.3 (red-black Gauss-Seidel smoothing, feature 5;
+ * residual restriction by linear interpolation, feature 3; flux-conserving
+ * prolongation, feature 4 with eqs. 13-14; exact coarsest solve, feature 6) to
+ * relative residual ||b_bar - L p||_2 / ||b_bar||_2 <= tol (the convergence test
+ * below eq. 15; the average reduction rate gamma of eq. (15) is reported in st).
  * rhs: device double [nz][ny][nx], not modified.  p: device double, in/out;
  * on entry the initial guess, on return the mean-zero solution (or the last
- * iterate).  st (optional, host): statistics.  Blocking on return.
- * A zero b_bar gives p = 0 and MG_OK.
+ * iterate).  Both must be 16-byte aligned (the finest-level passes access them
+ * as 16-byte vectors; torch allocations are).  st (optional, host): statistics.
+ * Blocking on return.  A zero b_bar gives p = 0 and MG_OK.
  * Errors: MG_E_NOT_CONVERGED (p = last iterate, st valid), MG_E_DIVERGED,
- * MG_E_INVALID (NULL handle/array, tol not finite or < 0), MG_E_HIP.
+ * MG_E_INVALID (NULL handle/array, rhs or p not 16-byte aligned, tol not finite
+ * or < 0; nothing is launched), MG_E_HIP.
  */
 mg_status mg_solve(mg_handle *h, const double *rhs, double *p, double tol, mg_stats *st,
                    void *stream);
@@ -271,8 +283,8 @@ mg_status mg_correct_velocity(const mg_handle *h, const double *p, double scale,
  * mean-zero pressure out, in the h^2-scaled units of eq. 10).  u, v, w: in/out:
  * u* in, projected velocity out.  st: as in mg_solve.  Blocking on return.
  * If the solve does not succeed, its status is returned and u, v, w are left
- * unchanged (b and p hold what the solve left).  Errors: those of mg_solve, and
- * MG_E_INVALID for a bad dt or h.
+ * unchanged (b and p hold what the solve left).  b and p must be 16-byte aligned,
+ * as in mg_solve.  Errors: those of mg_solve, and MG_E_INVALID for a bad dt or h.
  */
 mg_status mg_project(mg_handle *h, double *u, double *v, double *w, double dt, double hcell, double *b,
                      double *p, double tol, mg_stats *st, void *stream);
@@ -308,8 +320,13 @@ typedef struct mg_server mg_server;
 
 typedef struct {
     mg_options solver;    /* options for every request (precision, sweeps, ...) */
-    int max_slots;        /* concurrent resident problems, 1..256; the server creates one
-                             HIP stream (default priority) per slot */
+    int max_slots;        /* concurrent resident problems, 1..256 */
+    int nstreams;         /* entries of `streams`, 0..256; 0: the server creates max_slots HIP
+                             streams of its own (default priority) */
+    void *const *streams; /* caller-created hipStream_t handles (for example torch streams, which
+                             must have the default priority); the server runs all device work of
+                             its requests on them and never destroys them.  They must outlive the
+                             server.  The array itself is copied by mg_server_create. */
 } mg_server_options;
 
 typedef struct {
@@ -318,6 +335,10 @@ typedef struct {
     const double *rhs;            /* device right-hand side */
     double *p;                    /* device in/out: initial guess, then the solution */
     double tol;
+    void *stream;                 /* the stream on which the caller produced bx, by, bz, rhs and p
+                                     (NULL: the default stream).  mg_batch_submit records an event
+                                     on it; the server's work on the request starts after that
+                                     event, so writes enqueued there before the submit are seen. */
 } mg_request;
 
 typedef struct {
@@ -342,9 +363,14 @@ mg_status mg_server_create(void *arena, size_t arena_bytes, const mg_server_opti
                            mg_server **out);
 
 /*
- * Queue one solve.  The request's arrays must stay valid until mg_poll reports a
- * final status.  Thread-safe.  Errors: MG_E_BUDGET (workspace larger than the
- * whole arena), MG_E_INVALID.
+ * Queue one solve (the pressure equation (9) in the form of eq. (10), as mg_solve).
+ * The request's arrays must stay valid until mg_poll reports a final status; the
+ * server reads them only after the work the caller enqueued on r->stream before
+ * this call (an event is recorded there now).  When mg_poll reports a final status
+ * the solution in r->p is complete (the server has synchronised its own stream).
+ * rhs and p must be 16-byte aligned, as in mg_solve.
+ * Thread-safe.  Errors: MG_E_BUDGET (workspace larger than the whole arena),
+ * MG_E_INVALID, MG_E_HIP (event record failed).
  */
 mg_status mg_batch_submit(mg_server *s, const mg_request *r, uint64_t *ticket);
 

@@ -100,6 +100,9 @@ mg_status setup_launch(mg_handle* h, const double* bx, const double* by, const d
 mg_status setup_finish(mg_handle* h);
 inline int* setup_flags(mg_handle* h) { return reinterpret_cast<int*>(h->host + 14); }
 mg_status solve_impl(mg_handle* h, const double* rhs, double* p, double tol, mg_stats* st);
+// The solve's level-0 passes read and write p and b with 16-byte vector accesses:
+// MG_E_INVALID (with a message) unless both are 16-byte aligned.
+mg_status check_solve_arrays(const double* rhs, const double* p);
 
 // Solve as a state machine, so that a scheduler can interleave many problems.
 struct SolveState {

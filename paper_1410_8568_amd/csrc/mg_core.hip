@@ -1071,6 +1071,14 @@ mg_status solve_impl(mg_handle* h, const double* rhs, double* p, double tol, mg_
     return (mg_status)S.status;
 }
 
+mg_status check_solve_arrays(const double* rhs, const double* p) {
+    if (((uintptr_t)rhs & 15) || ((uintptr_t)p & 15)) {
+        set_error("rhs and p must be 16-byte aligned");
+        return MG_E_INVALID;
+    }
+    return MG_OK;
+}
+
 const char* last_error() { return g_err.c_str(); }
 
 }  // namespace mgrt
@@ -1114,7 +1122,7 @@ mg_status mg_workspace_bytes(const mg_grid* g, const mg_options* o, size_t* byte
 }
 
 mg_status mg_setup(const mg_grid* g, const mg_options* o, const double* bx, const double* by, const double* bz,
-                   int bc, void* ws, size_t ws_bytes, void* stream, mg_handle** out) {
+                   mg_bc bc, void* ws, size_t ws_bytes, void* stream, mg_handle** out) {
     try {
         if (!out || !bx || !by || !bz) {
             set_error("null argument");
@@ -1167,6 +1175,7 @@ mg_status mg_solve(mg_handle* h, const double* rhs, double* p, double tol, mg_st
             set_error("null handle/array or invalid tolerance");
             return MG_E_INVALID;
         }
+        if (check_solve_arrays(rhs, p) != MG_OK) return MG_E_INVALID;
         h->stream = (hipStream_t)stream;
         return solve_impl(h, rhs, p, tol, st);
     } catch (...) {

@@ -220,6 +220,7 @@ mg_status mg_project(mg_handle* h, double* u, double* v, double* w, double dt, d
             set_error("null handle/array, dt or h not finite and > 0, or invalid tolerance");
             return MG_E_INVALID;
         }
+        if (mgrt::check_solve_arrays(b, p) != MG_OK) return MG_E_INVALID;
         hipStream_t s = (hipStream_t)stream;
         mg_status r = launch_divergence(h->g, u, v, w, hcell / dt, b, s);
         if (r != MG_OK) return r;

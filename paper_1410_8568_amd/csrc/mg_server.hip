@@ -42,6 +42,7 @@ struct Job {
     mg_handle* h = nullptr;
     SolveState S;
     hipEvent_t ev = nullptr;
+    hipEvent_t ready = nullptr;   // recorded on the caller's stream at submit
     bool begin_pending = false;   // setup and the initial residual are in flight
     JobState state = QUEUED;
     mg_result result;
@@ -58,7 +59,8 @@ struct mg_server {
     std::deque<Job*> queue;
     std::unordered_map<uint64_t, Job*> jobs;
     std::vector<Job*> active;
-    std::vector<hipStream_t> streams;
+    std::vector<hipStream_t> streams;   // slot s runs on streams[s % streams.size()]
+    bool own_streams = false;
     std::vector<int> slot_free;
     std::vector<hipEvent_t> events;
     mgrt::Arena alloc;
@@ -74,7 +76,12 @@ struct mg_server {
 
 namespace {
 
+hipStream_t slot_stream(const mg_server* sv, int slot) { return sv->streams[(size_t)slot % sv->streams.size()]; }
+
 void complete(mg_server* sv, Job* j, int status) {
+    // work already queued for this job (setup, tuning, a partly launched
+    // iteration on a failure path) must end before its memory is handed out again
+    if (j->slot >= 0) (void)hipStreamSynchronize(slot_stream(sv, j->slot));
     solve_release(j->S);
     std::lock_guard<std::mutex> lk(sv->mu);
     j->result.status = status;
@@ -104,7 +111,13 @@ bool start_job(mg_server* sv, Job* j) {
     h->o.graph = 1;
     plan(&h->g, &h->o, &h->L);
     h->ws = sv->arena + j->off;
-    h->stream = sv->streams[j->slot];
+    h->stream = slot_stream(sv, j->slot);
+    // nothing of this request is read before the caller's producer work
+    if (hipStreamWaitEvent(h->stream, j->ready, 0) != hipSuccess) {
+        delete h;
+        complete(sv, j, MG_E_HIP);
+        return false;
+    }
     if (hipHostMalloc((void**)&h->host, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         h->host = nullptr;
         delete h;
@@ -229,10 +242,15 @@ extern "C" {
 mg_status mg_server_create(void* arena, size_t arena_bytes, const mg_server_options* o, mg_server** out) {
     try {
         if (!arena || !o || !out || ((uintptr_t)arena & 255) || arena_bytes == 0 || o->max_slots < 1 ||
-            o->max_slots > 256) {
-            set_error("null/misaligned arena, null options/out, or max_slots outside 1..256");
+            o->max_slots > 256 || o->nstreams < 0 || o->nstreams > 256 || (o->nstreams > 0 && !o->streams)) {
+            set_error("null/misaligned arena, null options/out, max_slots outside 1..256, or a bad stream list");
             return MG_E_INVALID;
         }
+        for (int s = 0; s < o->nstreams; s++)
+            if (!o->streams[s]) {
+                set_error("null stream in the server's stream list");
+                return MG_E_INVALID;
+            }
         mg_grid probe{8, 8, 8};
         Layout L;
         mg_status r = plan(&probe, &o->solver, &L);
@@ -243,18 +261,28 @@ mg_status mg_server_create(void* arena, size_t arena_bytes, const mg_server_opti
         sv->o = *o;
         sv->alloc.reset(arena_bytes & ~(size_t)255);
         sv->t0 = std::chrono::steady_clock::now();
-        for (int s = 0; s < o->max_slots; s++) {
-            hipStream_t st;
-            hipEvent_t ev;
-            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-                set_error("stream/event creation failed");
+        auto fail = [&](const char* msg) {
+            set_error(msg);
+            if (sv->own_streams)
                 for (auto x : sv->streams) (void)hipStreamDestroy(x);
-                for (auto x : sv->events) (void)hipEventDestroy(x);
-                delete sv;
-                return MG_E_HIP;
+            for (auto x : sv->events) (void)hipEventDestroy(x);
+            delete sv;
+            return MG_E_HIP;
+        };
+        if (o->nstreams > 0) {
+            for (int s = 0; s < o->nstreams; s++) sv->streams.push_back((hipStream_t)o->streams[s]);
+        } else {
+            sv->own_streams = true;
+            for (int s = 0; s < o->max_slots; s++) {
+                hipStream_t st;
+                if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+                    return fail("stream creation failed");
+                sv->streams.push_back(st);
             }
-            sv->streams.push_back(st);
+        }
+        for (int s = 0; s < o->max_slots; s++) {
+            hipEvent_t ev;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return fail("event creation failed");
             sv->events.push_back(ev);
             sv->slot_free.push_back(1);
         }
@@ -273,6 +301,7 @@ mg_status mg_batch_submit(mg_server* sv, const mg_request* r, uint64_t* ticket) 
             set_error("null server/request/array or bad tolerance");
             return MG_E_INVALID;
         }
+        if (check_solve_arrays(r->rhs, r->p) != MG_OK) return MG_E_INVALID;
         Layout L;
         mg_status st = plan(&r->grid, &sv->o.solver, &L);
         if (st != MG_OK) return st;
@@ -285,9 +314,17 @@ mg_status mg_batch_submit(mg_server* sv, const mg_request* r, uint64_t* ticket) 
         j->req = *r;
         j->bytes = bytes;
         memset(&j->result, 0, sizeof j->result);
+        if (hipEventCreateWithFlags(&j->ready, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(j->ready, (hipStream_t)r->stream) != hipSuccess) {
+            if (j->ready) (void)hipEventDestroy(j->ready);
+            delete j;
+            set_error("could not record the request's ready event on its stream");
+            return MG_E_HIP;
+        }
         {
             std::lock_guard<std::mutex> lk(sv->mu);
             if (sv->stop) {
+                (void)hipEventDestroy(j->ready);
                 delete j;
                 set_error("server is shutting down");
                 return MG_E_INVALID;
@@ -322,6 +359,7 @@ mg_status mg_poll(mg_server* sv, uint64_t ticket, mg_result* out) {
     if (out) *out = j->result;
     mg_status s = (mg_status)j->result.status;
     sv->jobs.erase(it);
+    if (j->ready) (void)hipEventDestroy(j->ready);
     delete j;
     return s;
 }
@@ -334,8 +372,12 @@ void mg_server_destroy(mg_server* sv) {
     }
     sv->cv.notify_all();
     if (sv->th.joinable()) sv->th.join();
-    for (auto& kv : sv->jobs) delete kv.second;
-    for (auto x : sv->streams) (void)hipStreamDestroy(x);
+    for (auto& kv : sv->jobs) {
+        if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+        delete kv.second;
+    }
+    if (sv->own_streams)
+        for (auto x : sv->streams) (void)hipStreamDestroy(x);
     for (auto x : sv->events) (void)hipEventDestroy(x);
     delete sv;
 }

@@ -32,7 +32,7 @@ __all__ = [
     "Problem", "smoothed_heaviside", "cell_centres", "faces_from_alpha",
     "divergence_rhs", "velocity_field", "normal_rhs", "drop_splash_levelset", "sphere_problem", "drop_splash_problem",
     "config0", "config1", "config2", "batch_problems", "request_stream",
-    "layered_problem", "constant_problem",
+    "layered_problem", "layered_profile", "constant_problem",
 ]
 
 
@@ -324,6 +324,21 @@ def layered_problem(n, seed=7, ratio=1000.0, depth=0.3) -> Problem:
     bz1 = np.random.default_rng(seed).standard_normal(nz)
     b = np.broadcast_to(bz1[:, None, None], (nz, ny, nx)).copy()
     return Problem(dims, bx, by, bz, b, dict(kind="layered", n=n, ratio=ratio, seed=seed))
+
+
+def layered_profile(n, seed=7, ratio=1000.0, depth=0.3):
+    """The z profiles of ``layered_problem(n, ...)`` without the 3-D arrays, for
+    grids too large to build on the host: (alpha per layer [n], z-faces [n+1] with
+    walls 0, rhs per layer [n]).  Broadcasting them (x- and y-faces equal to the
+    layer's alpha, the arithmetic mean of two equal values) reproduces
+    ``layered_problem`` value for value."""
+    zc = cell_centres(n)
+    ind = smoothed_heaviside(depth - zc, 1.5 / n)
+    alpha = 1.0 / (1.0 + (ratio - 1.0) * ind)
+    bz = np.zeros(n + 1)
+    bz[1:n] = 0.5 * (alpha[:-1] + alpha[1:])
+    b = np.random.default_rng(seed).standard_normal(n)
+    return alpha, bz, b
 
 
 def constant_problem(n, seed=8, beta=1.0) -> Problem:

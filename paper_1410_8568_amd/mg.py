@@ -71,13 +71,14 @@ class Stats(ctypes.Structure):
 
 
 class ServerOptions(ctypes.Structure):
-    _fields_ = [("solver", Options), ("max_slots", ctypes.c_int)]
+    _fields_ = [("solver", Options), ("max_slots", ctypes.c_int), ("nstreams", ctypes.c_int),
+                ("streams", ctypes.POINTER(ctypes.c_void_p))]
 
 
 class Request(ctypes.Structure):
     _fields_ = [("grid", Grid), ("bx", ctypes.c_void_p), ("by", ctypes.c_void_p),
                 ("bz", ctypes.c_void_p), ("rhs", ctypes.c_void_p), ("p", ctypes.c_void_p),
-                ("tol", ctypes.c_double)]
+                ("tol", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -351,14 +352,22 @@ class Solver:
 class Server:
     """Continuous-batching solve server over a torch uint8 arena (the HBM budget).
 
-    ``submit`` queues a solve and returns a ticket; the caller keeps the request's
-    tensors alive until ``poll`` returns a result (the binding holds references)."""
+    The server's device work runs on torch streams (``nstreams`` of them, default
+    priority) created here and passed to the library.  ``submit`` queues a solve and
+    returns a ticket; the server starts on it after the work already enqueued on the
+    submitting stream (the current torch stream by default).  The caller keeps the
+    request's tensors alive until ``poll`` returns a result (the binding holds
+    references)."""
 
-    def __init__(self, arena_bytes, precision="fp64", max_slots=16, device="cuda", **kw):
+    def __init__(self, arena_bytes, precision="fp64", max_slots=16, device="cuda", nstreams=None, **kw):
         import torch
         self.arena = torch.empty(arena_bytes + 256, dtype=torch.uint8, device=device)
         self._arena_ptr = (self.arena.data_ptr() + 255) & ~255
-        self.opts = ServerOptions(options(precision=precision, **kw), max_slots)
+        n = max_slots if nstreams is None else nstreams
+        self.streams = [torch.cuda.Stream(device=self.arena.device) for _ in range(n)]
+        self._stream_arr = (ctypes.c_void_p * max(n, 1))(*[s.cuda_stream for s in self.streams])
+        self.opts = ServerOptions(options(precision=precision, **kw), max_slots, n,
+                                  ctypes.cast(self._stream_arr, ctypes.POINTER(ctypes.c_void_p)))
         h = ctypes.c_void_p()
         st = lib().mg_server_create(ctypes.c_void_p(self._arena_ptr), ctypes.c_size_t(arena_bytes),
                                     ctypes.byref(self.opts), ctypes.byref(h))
@@ -367,7 +376,7 @@ class Server:
         self.h = h
         self._keep = {}
 
-    def submit(self, bx, by, bz, b, p, tol=1e-10):
+    def submit(self, bx, by, bz, b, p, tol=1e-10, stream=None):
         nz, ny, nxp = bx.shape
         n = (nxp - 1, ny, nz)
         nx = n[0]
@@ -376,7 +385,8 @@ class Server:
         _check_field(bz, (nz + 1, ny, nx), "bz")
         _check_field(b, (nz, ny, nx), "b")
         _check_field(p, (nz, ny, nx), "p")
-        r = Request(Grid(*n), bx.data_ptr(), by.data_ptr(), bz.data_ptr(), b.data_ptr(), p.data_ptr(), tol)
+        r = Request(Grid(*n), bx.data_ptr(), by.data_ptr(), bz.data_ptr(), b.data_ptr(), p.data_ptr(), tol,
+                    _stream(stream))
         t = ctypes.c_uint64()
         st = lib().mg_batch_submit(self.h, ctypes.byref(r), ctypes.byref(t))
         if st != MG_OK:

@@ -195,23 +195,151 @@ def test_graph_replay_bit_identical(precision, n):
     assert np.array_equal(p, ref_p)
 
 
-def test_config2_full_size_matches_oracle():
-    """512^3 Fourier-perturbed drop splash in the benchmark's configuration
-    (coarsest 8^3, default options): both GPU solvers against the oracle's FP64
-    solve, and their residual recomputed with the oracle's operator."""
+@pytest.fixture(scope="module")
+def config2_reference():
+    """The 512^3 benchmark input and two oracle solves of it: p* to relative
+    residual 1e-13 (or stagnation), so that the oracle is not the parity
+    bottleneck, and the oracle's own FP32-refined solve to 1e-10."""
     P = inputs.config2(512)
-    ref = oracle.solve(P.bx, P.by, P.bz, P.b, tol=1e-10, n_coarsest=8)
-    assert ref["status"] == "converged"
+    star = oracle.solve(P.bx, P.by, P.bz, P.b, tol=1e-13, n_coarsest=8, max_cycles=60)
+    print(f"512^3 oracle p*: {star['status']} after {star['cycles']} cycles, "
+          f"relative residual {star['history'][-1]:.3e}", flush=True)
+    assert star["history"][-1] <= 1e-12
+    ref32 = oracle.solve(P.bx, P.by, P.bz, P.b, tol=1e-10, n_coarsest=8, precision="fp32_refined")
+    assert ref32["status"] == "converged"
+    return P, star["p"], ref32
+
+
+def test_config2_full_size_matches_oracle(config2_reference):
+    """512^3 Fourier-perturbed drop splash in the benchmark's configuration
+    (coarsest 8^3, default options): both GPU solvers at the benchmark's tolerance
+    1e-10 against the oracle's p* (relative residual <= 1e-12), the FP32-refined one
+    also against the oracle's own FP32-refined solve, and their residual recomputed
+    with the oracle's operator.  The margins to the 1e-8 bar are printed; the
+    warm-started continuation to 1e-11 and 1e-12 shows the error shrinking with
+    the residual (the error is bounded by the condition number times the residual)."""
+    import torch
+    from paper_1410_8568_amd import mg
+    P, pstar, ref32 = config2_reference
     bbar = P.b - P.b.mean()
     nb = np.linalg.norm(bbar)
+    bx, by, bz, b = mg.to_device(P)
     for precision in ("fp64", "fp32_refined"):
-        p, st = gpu_solve(P, precision=precision, tol=1e-10, n_coarsest=8)
+        S = mg.Solver(bx, by, bz, precision=precision, n_coarsest=8)
+        pt = torch.zeros_like(b)
+        st = S.solve(b, pt, tol=1e-10)
         assert st["rc"] == 0, st
+        p = pt.cpu().numpy()
         r = oracle.residual(P.bx, P.by, P.bz, p, bbar)
         assert np.linalg.norm(r) / nb <= 1e-10
         assert abs(p.mean()) <= 1e-12 * np.abs(p).max()
-        err = rel(p, ref["p"])
-        print(f"512^3 {precision}: cycles {st['cycles']} rel residual {st['rel_residual']:.3e} "
-              f"oracle rel err {err:.3e}", flush=True)
+        err = rel(p, pstar)
+        msg = (f"512^3 {precision}: cycles {st['cycles']} rel residual {st['rel_residual']:.3e} "
+               f"error vs p* {err:.3e} (margin {1e-8 / err:.1f}x)")
+        if precision == "fp32_refined":
+            err32 = rel(p, ref32["p"])
+            msg += f", vs the oracle's FP32-refined solve {err32:.3e}"
+        print(msg, flush=True)
         assert err <= 1e-8
+        if precision == "fp32_refined":
+            assert err32 <= 1e-8
+        for tol in (1e-11, 1e-12):
+            st2 = S.solve(b, pt, tol=tol)
+            print(f"  continued to {tol:g}: rel residual {st2['rel_residual']:.3e} "
+                  f"error vs p* {rel(pt.cpu().numpy(), pstar):.3e}", flush=True)
+        S.close()
+        del p, pt
+
+
+def _layered_on_device(n, dev="cuda"):
+    """The layered problem of n^3 cells built on the device from its z profiles."""
+    import torch
+    a, bz1, b1 = inputs.layered_profile(n)
+    ta = torch.from_numpy(a).to(dev)[:, None, None]
+    bx = torch.zeros((n, n, n + 1), dtype=torch.float64, device=dev)
+    bx[:, :, 1:n] = ta
+    by = torch.zeros((n, n + 1, n), dtype=torch.float64, device=dev)
+    by[:, 1:n, :] = ta
+    bz = torch.from_numpy(bz1).to(dev)[:, None, None].expand(n + 1, n, n).contiguous()
+    b = torch.from_numpy(b1).to(dev)[:, None, None].expand(n, n, n).contiguous()
+    return (bx, by, bz, b), bz1, b1
+
+
+def test_layered_closed_form_1024():
+    """The largest benchmark size: 1024^3 with coefficients and rhs varying in z
+    only (a flat film, density ratio 1000).  The exact solution is the 1-D flux
+    form (a closed form, no oracle); both GPU solvers from p = 0 to relative
+    residual 1e-10, the error printed with its margin to the 1e-8 bar.  Where the
+    residual tolerance does not give 1e-8 the solve continues to tighter residuals
+    and the residual at which it holds is printed (a tolerance on the residual, never
+    on the error)."""
+    import torch
+    from paper_1410_8568_amd import mg
+    n = 1024
+    (bx, by, bz, b), bz1, b1 = _layered_on_device(n)
+    p1 = torch.from_numpy(pins.layered_solve(bz1, b1)).cuda()[:, None, None]
+    norm_star = float(torch.linalg.vector_norm(p1.expand(n, n, n)))
+
+    def err_of(p):
+        return float(torch.linalg.vector_norm(p - p1)) / norm_star
+
+    for precision in ("fp32_refined", "fp64"):
+        S = mg.Solver(bx, by, bz, precision=precision, n_coarsest=8)
+        p = torch.zeros_like(b)
+        st = S.solve(b, p, tol=1e-10)
+        assert st["rc"] == 0, st
+        err = err_of(p)
+        print(f"1024^3 layered {precision}: cycles {st['cycles']} rel residual {st['rel_residual']:.3e} "
+              f"error {err:.3e}", flush=True)
+        tol, holds_at = 1e-10, (st["rel_residual"] if err <= 1e-8 else None)
+        while holds_at is None and tol > 1e-13:
+            tol /= 10
+            st = S.solve(b, p, tol=tol)
+            err = err_of(p)
+            print(f"  continued to {tol:g}: rel residual {st['rel_residual']:.3e} error {err:.3e}", flush=True)
+            if err <= 1e-8:
+                holds_at = st["rel_residual"]
+        print(f"  1e-8 holds at relative residual {holds_at}", flush=True)
+        assert holds_at is not None
+        S.close()
         del p
+
+
+@pytest.mark.parametrize("precision,krylov", [("fp64", "none"), ("fp32_refined", "none"), ("fp64", "fcg")])
+def test_level0_column_residual_kernels(precision, krylov):
+    """A level-0 plane of 1024 x 512 cells (more than 512 x 512) sends the finest
+    residual of every mode (convergence norm, refinement residual with its FP32
+    copy, Krylov residual) through the cell-pair column kernels instead of the flat
+    one; the grid coarsens 1024x512x32 -> ... -> 32x16x1 (512 cells, solved
+    exactly).  Histories and p against the oracle."""
+    n = (1024, 512, 32)
+    P = ragged_problem(n, seed=17)
+    ref = oracle.solve(P.bx, P.by, P.bz, P.b, tol=1e-10, precision=precision, krylov=krylov)
+    assert ref["status"] == "converged"
+    p, st = gpu_solve(P, precision=precision, tol=1e-10, krylov=krylov)
+    assert st["rc"] == 0, st
+    assert st["levels"] == 6
+    check_history(st["history"], ref["history"], precision)
+    err = rel(p, ref["p"])
+    print(f"{n} {precision} {krylov}: cycles {st['cycles']} oracle rel err {err:.3e}", flush=True)
+    assert err <= 1e-8
+
+
+def test_unaligned_solve_arrays_rejected():
+    """p or rhs 8 bytes past a 16-byte boundary: refused before any launch."""
+    import torch
+    from paper_1410_8568_amd import mg
+    P = inputs.config0()
+    bx, by, bz, b = mg.to_device(P)
+    S = mg.Solver(bx, by, bz)
+    buf = torch.zeros(b.numel() + 1, dtype=torch.float64, device="cuda")
+    pu = buf[1:].view(b.shape)
+    assert pu.data_ptr() % 16 == 8
+    st = S.solve(b, pu, check=False)
+    assert st["rc"] == mg.MG_E_INVALID
+    bu = torch.empty_like(buf)[1:].view(b.shape)
+    bu.copy_(b)
+    st = S.solve(bu, torch.zeros_like(b), check=False)
+    assert st["rc"] == mg.MG_E_INVALID
+    assert torch.count_nonzero(buf).item() == 0
+    S.close()

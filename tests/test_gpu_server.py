@@ -90,3 +90,49 @@ def test_budget_and_errors():
         srv.poll(tk[0])
     assert ei.value.status == mg.MG_E_NOT_FOUND
     srv.close()
+
+
+@pytest.mark.parametrize("nstreams", [1, 3])
+def test_submit_waits_for_producer_stream(nstreams):
+    """The request's rhs and initial guess are written on a busy torch stream just
+    before the submit; the server (running on torch streams passed in its options,
+    fewer streams than slots) must read them only after that work, so the result
+    equals the alone solve bit for bit.  Reading early would see the stale guess of
+    1e3 (or an unwritten rhs) and give another iterate."""
+    import torch
+    from paper_1410_8568_amd import mg
+    probs = inputs.batch_problems(3, sizes=(32, 64))
+    dev = [mg.to_device(P) for P in probs]
+    alone = []
+    for (bx, by, bz, b) in dev:
+        S = mg.Solver(bx, by, bz, precision="fp32_refined")
+        p = torch.zeros_like(b)
+        st = S.solve(b, p, tol=1e-10)
+        assert st["rc"] == 0
+        alone.append((p.clone(), st))
+        S.close()
+    srv = mg.Server(1 << 30, precision="fp32_refined", max_slots=4, nstreams=nstreams)
+    assert len(srv.streams) == nstreams
+    prod = torch.cuda.Stream()
+    big = torch.randn(4096, 4096, device="cuda")
+    torch.cuda.synchronize()
+    outs, tickets = [], []
+    for rep in range(2):
+        for (bx, by, bz, b) in dev:
+            p = torch.full_like(b, 1e3)
+            bb = torch.empty_like(b)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(prod):
+                for _ in range(8):          # keep the producer stream busy for a while
+                    big = (big @ big).clamp_(-1.0, 1.0)
+                p.zero_()
+                bb.copy_(b)
+                tickets.append(srv.submit(bx, by, bz, bb, p, tol=1e-10, stream=prod))
+            outs.append((p, bb))
+    results = [srv.wait(t) for t in tickets]
+    srv.close()
+    for q, (res, (p, _)) in enumerate(zip(results, outs)):
+        ref_p, ref_st = alone[q % len(dev)]
+        assert res["rc"] == 0, res
+        assert res["stats"]["history"] == ref_st["history"], q
+        assert torch.equal(p, ref_p), q

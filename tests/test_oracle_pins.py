@@ -437,3 +437,15 @@ def test_generator_divergence_rhs_is_compatible():
     assert np.all(P.bx[:, :, 1:-1] > 0) and np.all(P.bx[:, :, [0, -1]] == 0)
     ratio = P.bx[:, :, 1:-1].max() / P.bx[:, :, 1:-1].min()
     assert 900 < ratio < 1001
+
+
+@pytest.mark.parametrize("n", [16, 48])
+def test_layered_profile_reproduces_layered_problem(n):
+    """The 1-D profiles used to build the 1024^3 layered case on the device are
+    the layered problem's own values, so its closed form applies there too."""
+    P = inputs.layered_problem(n)
+    a, bz, b = inputs.layered_profile(n)
+    assert np.array_equal(P.bz, np.broadcast_to(bz[:, None, None], P.bz.shape))
+    assert np.array_equal(P.bx[:, :, 1:-1], np.broadcast_to(a[:, None, None], (n, n, n - 1)))
+    assert np.array_equal(P.by[:, 1:-1, :], np.broadcast_to(a[:, None, None], (n, n - 1, n)))
+    assert np.array_equal(P.b, np.broadcast_to(b[:, None, None], P.b.shape))
