@@ -5,10 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/mg.h"
+#include "mg_launch.h"
 
 
 namespace mgrt {
@@ -66,6 +68,11 @@ struct mg_handle {
     int* flag = nullptr;
     double *kr = nullptr, *kz = nullptr, *ks = nullptr, *kq = nullptr;   // Krylov: r, z, s, q
     hipStream_t stream = nullptr;
+    // batch context of the cycle launches (one problem: base == nullptr, nslots == 1)
+    // and, while a graph is being built, the recording that receives them
+    const uintptr_t* bt_base = nullptr;
+    int bt_slots = 1;
+    mgrt::Recording* rec = nullptr;
     double* host = nullptr;  // pinned host copy of device scalars
     int tile[MG_MAX_LEVELS];   // smoother variant per level
     int rtile[MG_MAX_LEVELS];  // variant of the fused pre-smoothing + restriction pass (0: none)
@@ -82,6 +89,16 @@ struct mg_handle {
 };
 
 namespace mgrt {
+// The launcher of a handle's cycle kernels: its stream, batch context and recording.
+inline Launcher launcher(const mg_handle* h) {
+    Launcher l;
+    l.stream = h->stream;
+    l.base = h->bt_base;
+    l.nslots = h->bt_slots;
+    l.rec = h->rec;
+    return l;
+}
+
 // Bracket a kernel launch with profiling events when enabled.
 struct Prof {
     mg_handle* h;
@@ -115,14 +132,17 @@ struct SolveState {
     int it = 0;
     int status = MG_OK;
     bool project = false;  // p still needs its final mean-zero projection
-    hipGraph_t graph = nullptr;          // one captured iteration (options.graph)
+    hipGraph_t graph = nullptr;          // one iteration's launches as a graph (options.graph)
     hipGraphExec_t gexec = nullptr;
+    std::shared_ptr<Recording> rec;      // the launches the graph was built from (kept with it)
     bool graph_failed = false;
     std::chrono::steady_clock::time_point t0;
 };
 mg_status solve_begin_launch(SolveState& S);      // asynchronous: projection + initial residual
 mg_status solve_begin_finish(SolveState& S);      // after h->stream is synchronised
 mg_status solve_launch_iteration(SolveState& S);  // asynchronous: one (outer) iteration
+// The launches of one (outer) iteration, on the handle's launcher (direct or recorded).
+mg_status launch_iteration_kernels(SolveState& S);
 void solve_after_sync(SolveState& S);             // after h->stream is synchronised
 bool solve_running(const SolveState& S);
 void solve_end(SolveState& S, mg_stats* st);

@@ -382,7 +382,7 @@ struct Hier {
 };
 
 template <class T, int TX, int TY, int NSW, bool RES = false>
-static void launch_sweep(hipStream_t s, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0, int target,
+static void launch_sweep(const Launcher& ln, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0, int target,
                          const double* shift_sum, int zero_in, T* rc, double omega) {
     const int gx = (L.nx + TX - 1) / TX, gy = (L.ny + TY - 1) / TY;
     const int tiles = gx * gy;
@@ -393,11 +393,11 @@ static void launch_sweep(hipStream_t s, const Lvl<T>& L, const T* pin, T* pout, 
     chunks = (L.nz + kc - 1) / kc;
     constexpr int NT = (TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES ? 2 : 0));
     if (omega != 1.0)   // successive over-relaxation (a separate instantiation)
-        k_rb_sweep<T, TX, TY, NSW, RES, true><<<dim3(tiles * chunks), NT, 0, s>>>(
-            L, pin, pout, b, c0, kc, gx, gy, shift_sum, (double)L.nx * L.ny * L.nz, zero_in, rc, (T)omega);
+        ln.x(k_rb_sweep<T, TX, TY, NSW, RES, true>, tiles * chunks, NT, L, pin, pout, b, c0, kc, gx, gy, shift_sum,
+             (double)L.nx * L.ny * L.nz, zero_in, rc, (T)omega);
     else
-        k_rb_sweep<T, TX, TY, NSW, RES, false><<<dim3(tiles * chunks), NT, 0, s>>>(
-            L, pin, pout, b, c0, kc, gx, gy, shift_sum, (double)L.nx * L.ny * L.nz, zero_in, rc, T(1));
+        ln.x(k_rb_sweep<T, TX, TY, NSW, RES, false>, tiles * chunks, NT, L, pin, pout, b, c0, kc, gx, gy, shift_sum,
+             (double)L.nx * L.ny * L.nz, zero_in, rc, T(1));
 }
 
 // Fused variant v (1..MG_NUM_TILES): tile (v - 1) / 3 of the list (four one-sweep
@@ -419,7 +419,7 @@ static bool variant_native(int v) {
 
 // Fused sweep variant v in 1..MG_NUM_TILES: one pass doing sweeps_per_pass(v) sweeps.
 template <class T>
-static void fused_sweep(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0,
+static void fused_sweep(const Launcher& s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0,
                         const double* shift_sum = nullptr, int zero_in = 0, double omega = 1.0) {
     const int target = variant_target(v);
     switch ((v - 1) / 3) {
@@ -457,7 +457,7 @@ static bool has_restrict_variant(int v) {
 // restricts it into rc (the next level's right-hand side); returns false
 // (nothing launched) when v has no such pass.
 template <class T>
-static bool fused_sweep_restrict(hipStream_t s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b,
+static bool fused_sweep_restrict(const Launcher& s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b,
                                  const double* shift_sum, int zero_in, T* rc, double omega = 1.0) {
     const int target = variant_target(v);
     switch ((v - 1) / 3) {
@@ -474,26 +474,26 @@ static bool fused_sweep_restrict(hipStream_t s, int v, const Lvl<T>& L, const T*
 }
 
 template <class T>
-static void ref_sweep(hipStream_t s, const Lvl<T>& L, T* p, const T* b, int c0, double omega = 1.0) {
+static void ref_sweep(const Launcher& ln, const Lvl<T>& L, T* p, const T* b, int c0, double omega = 1.0) {
     const dim3 g = col_grid(L.nx, L.ny, L.nz), blk(BX, BY);
-    k_rb_half<T><<<g, blk, 0, s>>>(L, p, b, c0, (T)omega);
-    k_rb_half<T><<<g, blk, 0, s>>>(L, p, b, 1 - c0, (T)omega);
+    ln.z(k_rb_half<T>, g, blk, L, p, b, c0, (T)omega);
+    ln.z(k_rb_half<T>, g, blk, L, p, b, 1 - c0, (T)omega);
 }
 
 // Residual of level L restricted into rc (the next level's right-hand side),
 // as a separate pass: 4 cells per thread in FP32 when nx allows, else 2.
 template <class T>
-static void launch_restrict(hipStream_t s, const Lvl<T>& L, const T* p, const T* b, T* rc) {
+static void launch_restrict(const Launcher& ln, const Lvl<T>& L, const T* p, const T* b, T* rc) {
     int nb = 0;
     if constexpr (sizeof(T) == 4) {
         if (L.nx % 4 == 0) {
             const ColGrid G = zgrid(L.nx / 4, L.ny, L.nz, true, &nb);
-            k_resid_restrict_cells<T, 4><<<nb, CBX * CBY, 0, s>>>(L, p, b, G, rc);
+            ln.x(k_resid_restrict_cells<T, 4>, nb, CBX * CBY, L, p, b, G, rc);
             return;
         }
     }
     const ColGrid G = zgrid(L.nx / 2, L.ny, L.nz, true, &nb);
-    k_resid_restrict_cells<T, 2><<<nb, CBX * CBY, 0, s>>>(L, p, b, G, rc);
+    ln.x(k_resid_restrict_cells<T, 2>, nb, CBX * CBY, L, p, b, G, rc);
 }
 
 // ------------------------------------------------------------------ smoother tuning
@@ -561,6 +561,8 @@ static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b
         }
     }
     hipStream_t s = h->stream;
+    Launcher ls;
+    ls.stream = s;
     const size_t n = (size_t)L.nx * L.ny * L.nz;
     HIPCHK(hipMemsetAsync(pin, 0, n * sizeof(T), s));
     if (b != pin) HIPCHK(hipMemsetAsync(b, 0, n * sizeof(T), s));
@@ -587,9 +589,9 @@ static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b
         if (v == 0 || (v > 0 && !variant_native<T>(v))) continue;
         float t = time_ms([&]() {
             if (v < 0)
-                ref_sweep<T>(s, L, pin, b, 0);
+                ref_sweep<T>(ls, L, pin, b, 0);
             else
-                fused_sweep<T>(s, v, L, pin, pout, b, 0);
+                fused_sweep<T>(ls, v, L, pin, pout, b, 0);
         });
         if (v > 0) t /= sweeps_per_pass(v);
         if (t < best) {
@@ -602,10 +604,10 @@ static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b
     bool any = false;
     for (int v = 1; v <= MG_NUM_TILES; v++) any = any || has_restrict_variant<T>(v);
     if (any) {
-        float rbest = 2.0f * best + time_ms([&]() { launch_restrict<T>(s, L, pin, b, rc); });
+        float rbest = 2.0f * best + time_ms([&]() { launch_restrict<T>(ls, L, pin, b, rc); });
         for (int v = 1; v <= MG_NUM_TILES; v++) {
             if (!has_restrict_variant<T>(v)) continue;
-            const float t = time_ms([&]() { fused_sweep_restrict<T>(s, v, L, pin, pout, b, nullptr, 0, rc); });
+            const float t = time_ms([&]() { fused_sweep_restrict<T>(ls, v, L, pin, pout, b, nullptr, 0, rc); });
             if (t < rbest) {
                 rbest = t;
                 bestr = v;
@@ -631,13 +633,13 @@ static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b
 template <class T>
 static bool smooth(mg_handle* h, Hier<T>& H, int l, int nsweep, int c0, T*& cur, T*& alt,
                    const double* shift_sum = nullptr, bool zero_in = false) {
-    hipStream_t s = h->stream;
+    const Launcher s = launcher(h);
     const LevelDims& d = H.d[l];
     const int tile = alt ? h->tile[l] : -1;
     const bool fused = tile > 0 && nsweep >= sweeps_per_pass(tile);
     if (zero_in && !fused) {
         Prof pf(h, MG_K_OTHER, (double)d.ncell() * sizeof(T));
-        k_fill<T><<<lin_grid(d.ncell()), 256, 0, s>>>(cur, d.ncell(), T(0));
+        s.x(k_fill<T>, lin_grid(d.ncell()).x, 256, cur, d.ncell(), T(0));
         zero_in = false;
     }
     if (nsweep <= 0) return shift_sum == nullptr;
@@ -672,18 +674,18 @@ static bool fused_first_sweep(const mg_handle* h) {
 
 template <class T>
 static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nullptr, bool zero_init = false) {
-    hipStream_t s = h->stream;
+    const Launcher s = launcher(h);
     const LevelDims& d = H.d[l];
     if (l == H.nlev - 1) {
         if (h->o.coarse_gmres > 0) {
             Prof pf(h, MG_K_COARSE, (2.0 * d.ncell() + 3.0 * d.ncell()) * 8.0);
-            k_coarse_gmres<T><<<1, 512, 0, s>>>(Lvl<double>{d.nx, d.ny, d.nz, h->bx[l], h->by[l], h->bz[l]},
-                                               H.rhs[l], H.e[l], h->o.coarse_gmres, h->o.coarse_gmres_tol,
-                                               h->o.coarse_gmres_maxit);
+            s.x(k_coarse_gmres<T>, 1, 512, Lvl<double>{d.nx, d.ny, d.nz, h->bx[l], h->by[l], h->bz[l]}, H.rhs[l],
+                H.e[l], h->o.coarse_gmres, h->o.coarse_gmres_tol, h->o.coarse_gmres_maxit);
             return;
         }
         Prof pf(h, MG_K_COARSE, (double)h->L.ncoarse * h->L.ncoarse * 8 + 2.0 * d.ncell() * sizeof(T));
-        k_coarse_solve<T><<<(h->L.ncoarse + 7) / 8, 512, 0, s>>>(h->binv, h->L.ncoarse, H.rhs[l], H.e[l]);
+        s.x(k_coarse_solve<T>, (h->L.ncoarse + 7) / 8, 512, (const double*)h->binv, h->L.ncoarse, (const T*)H.rhs[l],
+            H.e[l]);
         return;
     }
     // the current iterate moves between e and tmp as fused passes run
@@ -707,9 +709,8 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
         Prof pf(h, MG_K_RESTRICT, restrict_bytes + 2.0 * d.ncell() * sizeof(T));
         int nbr = 0;
         const ColGrid G = zgrid(d.nx / 2, d.ny, d.nz, false, &nbr);
-        k_resid_cells<T, 2, 2><<<nbr, CBX * CBY, 0, s>>>(H.L[l], cur, H.rhs[l], G, nullptr, nullptr, h->part,
-                                                         H.tmp[l]);
-        k_restrict64<T><<<lin_grid(c.ncell()), 256, 0, s>>>(H.tmp[l], d.nx, d.ny, d.nz, H.rhs[l + 1]);
+        s.x(k_resid_cells<T, 2, 2>, nbr, CBX * CBY, H.L[l], cur, H.rhs[l], G, nullptr, nullptr, h->part, H.tmp[l]);
+        s.x(k_restrict64<T>, lin_grid(c.ncell()).x, 256, H.tmp[l], d.nx, d.ny, d.nz, H.rhs[l + 1]);
     } else {
         smooth(h, H, l, h->o.nu1, 0, cur, alt, shift_sum, zero_init);
         Prof pf(h, MG_K_RESTRICT, restrict_bytes);
@@ -722,12 +723,12 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
         // columns: coarse x by fine y; chunks of coarse planes (FP32: about 8192 workgroups,
         // which measured 11% faster at 512^3 than 2048; FP64 is faster with 2048)
         const ColGrid G = zgrid(c.nx, d.ny, c.nz, false, &nbp, sizeof(T) == 4 ? 8192 : 2048);
-        k_prolong_col<T><<<nbp, CBX * CBY, 0, s>>>(H.e[l + 1], H.a[l + 1], c.nx, c.ny, c.nz, G, cur);
+        s.x(k_prolong_col<T>, nbp, CBX * CBY, H.e[l + 1], H.a[l + 1], c.nx, c.ny, c.nz, G, cur);
     }
     smooth(h, H, l, h->o.nu2, 1, cur, alt);
     if (cur != H.e[l]) {
         Prof pf(h, MG_K_OTHER, 2.0 * d.ncell() * sizeof(T));
-        HIPCHK_VOID(hipMemcpyAsync(H.e[l], cur, d.ncell() * sizeof(T), hipMemcpyDeviceToDevice, s));
+        s.x(k_copy<T>, lin_grid(d.ncell()).x, 256, H.e[l], cur, d.ncell());
     }
 }
 
@@ -736,13 +737,14 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
 // residual of a 512^3 grid leaves 131072 pairs, 55 us for one workgroup).
 static void finish(mg_handle* h, int nblk, int slot) {
     Prof pf(h, MG_K_OTHER, 16.0 * nblk);
+    const Launcher s = launcher(h);
     if (nblk > 4 * FIN_THREADS) {
         const int per = (nblk + FIN_PARTS - 1) / FIN_PARTS, g = (nblk + per - 1) / per;
         double* p2 = h->part + (size_t)2 * h->L.max_blocks;
-        k_finish2_part<<<g, FIN_THREADS, 0, h->stream>>>(h->part, nblk, per, p2);
-        k_finish2<<<1, FIN_THREADS, 0, h->stream>>>(p2, g, h->scal + slot);
+        s.x(k_finish2_part, g, FIN_THREADS, (const double*)h->part, nblk, per, p2);
+        s.x(k_finish2, 1, FIN_THREADS, (const double*)p2, g, h->scal + slot);
     } else {
-        k_finish2<<<1, FIN_THREADS, 0, h->stream>>>(h->part, nblk, h->scal + slot);
+        s.x(k_finish2, 1, FIN_THREADS, (const double*)h->part, nblk, h->scal + slot);
     }
 }
 
@@ -770,19 +772,19 @@ static void build_hier(mg_handle* h, double* p, Hier<double>& H64, Hier<float>& 
 // Residual pass over level 0 (FP64; MODE as k_resid_col): the cell-pair
 // kernel when nx is even.  Returns the number of partial-sum blocks.
 template <int MODE>
-static int launch_resid(hipStream_t s, const Lvl<double>& L, const double* p, const double* b,
+static int launch_resid(const Launcher& s, const Lvl<double>& L, const double* p, const double* b,
                         const double* inv_s, float* r32, double* part, double* r64 = nullptr) {
     int nb = 0;
     if (resid_flat_fits(LevelDims{L.nx, L.ny, L.nz}) && ((uintptr_t)p & 15) == 0 && ((uintptr_t)b & 15) == 0) {
         const uint32_t units = (uint32_t)((size_t)L.nx * L.ny * L.nz / 2);
         nb = (int)((units + RES_FLAT_THREADS - 1) / RES_FLAT_THREADS);
-        k_resid_flat<MODE><<<nb, RES_FLAT_THREADS, 0, s>>>(L, p, b, units, inv_s, r32, part, r64);
+        s.x(k_resid_flat<MODE>, nb, RES_FLAT_THREADS, L, p, b, units, inv_s, r32, part, r64);
     } else if ((L.nx & 1) == 0 && ((uintptr_t)p & 15) == 0) {
         const ColGrid G = zgrid(L.nx / 2, L.ny, L.nz, false, &nb);
-        k_resid_cells<double, 2, MODE><<<nb, CBX * CBY, 0, s>>>(L, p, b, G, inv_s, r32, part, r64);
+        s.x(k_resid_cells<double, 2, MODE>, nb, CBX * CBY, L, p, b, G, inv_s, r32, part, r64);
     } else {
         const ColGrid G = zgrid(L.nx, L.ny, L.nz, false, &nb);
-        k_resid_col<double, MODE><<<nb, CBX * CBY, 0, s>>>(L, p, b, G, inv_s, r32, part, r64);
+        s.x(k_resid_col<double, MODE>, nb, CBX * CBY, L, p, b, G, inv_s, r32, part, r64);
     }
     return nb;
 }
@@ -798,26 +800,26 @@ mg_status solve_begin_launch(SolveState& S) {
     S.it = 0;
     const LevelDims& d0 = h->L.d[0];
     const double N = (double)d0.ncell();
-    hipStream_t s = h->stream;
+    const Launcher s = launcher(h);
     const dim3 g0 = col_grid(d0.nx, d0.ny, d0.nz), blk(BX, BY);
     const int nb0 = (int)(g0.x * g0.y * g0.z);
     const bool f32 = h->o.precision == MG_FP32_REFINED;
     Lvl<double> L64{d0.nx, d0.ny, d0.nz, h->bx[0], h->by[0], h->bz[0]};
     {
         Prof pf(h, MG_K_OTHER, 8.0 * N);
-        k_sum_sq<double><<<g0, blk, 0, s>>>(S.rhs, d0.nx, d0.ny, d0.nz, h->part);
+        s.z(k_sum_sq<double>, g0, blk, S.rhs, d0.nx, d0.ny, d0.nz, h->part);
     }
     finish(h, nb0, 0);
     {
         Prof pf(h, MG_K_OTHER, 16.0 * N);
-        k_project<<<g0, blk, 0, s>>>(S.rhs, h->bbar, h->scal, d0.nx, d0.ny, d0.nz, h->part);
+        s.z(k_project, g0, blk, S.rhs, h->bbar, (const double*)h->scal, d0.nx, d0.ny, d0.nz, h->part);
     }
     finish(h, nb0, 2);
     const double resid_bytes = (2.0 * N + d0.nfaces()) * 8.0;
     int nbz = 0;
     if (f32) {
         // first FP32 right-hand side scaled by a power of two near the RMS of b_bar
-        k_refine_scale<<<1, 64, 0, s>>>(h->scal + 3, N, h->scal + 8);
+        s.x(k_refine_scale, 1, 64, (const double*)(h->scal + 3), N, h->scal + 8);
         Prof pf(h, MG_K_REFINE, resid_bytes + 4.0 * N);
         nbz = launch_resid<1>(s, L64, S.p, h->bbar, h->scal + 9, h->frhs[0], h->part);
     } else if (h->o.krylov == MG_KRYLOV_FCG) {
@@ -827,9 +829,9 @@ mg_status solve_begin_launch(SolveState& S) {
         }
         // no previous direction: s = q = 0 and s.q = 0 (so the first beta is 0)
         Prof pf(h, MG_K_KRYLOV, 16.0 * N);
-        k_fill<double><<<lin_grid(d0.ncell()), 256, 0, s>>>(h->ks, d0.ncell(), 0.0);
-        k_fill<double><<<lin_grid(d0.ncell()), 256, 0, s>>>(h->kq, d0.ncell(), 0.0);
-        k_fill<double><<<1, 64, 0, s>>>(h->scal + 12, 1, 0.0);
+        s.x(k_fill<double>, lin_grid(d0.ncell()).x, 256, h->ks, d0.ncell(), 0.0);
+        s.x(k_fill<double>, lin_grid(d0.ncell()).x, 256, h->kq, d0.ncell(), 0.0);
+        s.x(k_fill<double>, 1, 64, h->scal + 12, (size_t)1, 0.0);
     } else {
         Prof pf(h, MG_K_NORM, resid_bytes);
         nbz = launch_resid<0>(s, L64, S.p, h->bbar, nullptr, nullptr, h->part);
@@ -837,7 +839,7 @@ mg_status solve_begin_launch(SolveState& S) {
     finish(h, nbz, 4);
     S.project = true;  // scal[5] now holds sum(p); p is made mean-zero lazily
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(h->host, h->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h->host, h->scal, 6 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     return MG_OK;
 }
 
@@ -851,7 +853,7 @@ mg_status solve_begin_finish(SolveState& S) {
     S.norm_b = std::sqrt(h->host[3]);
     S.st.norm_b = S.norm_b;
     if (S.norm_b == 0.0) {
-        k_fill<double><<<lin_grid(d0.ncell()), 256, 0, h->stream>>>(S.p, d0.ncell(), 0.0);
+        launcher(h).x(k_fill<double>, lin_grid(d0.ncell()).x, 256, S.p, d0.ncell(), 0.0);
         HIPCHK(hipStreamSynchronize(h->stream));
         S.project = false;
         S.st.nhist = 1;
@@ -873,11 +875,11 @@ mg_status solve_begin_finish(SolveState& S) {
 // that rewrites p (the first fused pre-smoothing sweep, or the refinement
 // update) and, after the last iteration, done by solve_end.  The caller
 // synchronises h->stream before solve_after_sync.
-static mg_status launch_iteration_kernels(SolveState& S) {
+mg_status launch_iteration_kernels(SolveState& S) {
     mg_handle* h = S.h;
     const LevelDims& d0 = h->L.d[0];
     const double N = (double)d0.ncell();
-    hipStream_t s = h->stream;
+    const Launcher s = launcher(h);
     const dim3 g0 = col_grid(d0.nx, d0.ny, d0.nz), blk(BX, BY);
     const bool f32 = h->o.precision == MG_FP32_REFINED;
     const double resid_bytes = (2.0 * N + d0.nfaces()) * 8.0;
@@ -894,25 +896,29 @@ static mg_status launch_iteration_kernels(SolveState& S) {
         vcycle(h, HK, 0, nullptr, true);
         {
             Prof pf(h, MG_K_KRYLOV, 24.0 * N);
-            k_fcg_dots<<<g0, blk, 0, s>>>(h->kz, h->kq, h->kr, d0.nx, d0.ny, d0.nz, h->part);
+            s.z(k_fcg_dots, g0, blk, (const double*)h->kz, (const double*)h->kq, (const double*)h->kr, d0.nx, d0.ny,
+                d0.nz, h->part);
         }
         finish(h, (int)(g0.x * g0.y * g0.z), 10);
-        k_fcg_beta<<<1, 64, 0, s>>>(h->scal);
+        s.x(k_fcg_beta, 1, 64, h->scal);
         {
             Prof pf(h, MG_K_KRYLOV, (3.0 * N + d0.nfaces()) * 8.0);
             int nbd = 0;
             if ((d0.nx & 1) == 0) {
                 const ColGrid G = zgrid(d0.nx / 2, d0.ny, d0.nz, false, &nbd);
-                k_fcg_direction<2><<<nbd, CBX * CBY, 0, s>>>(L64, h->kz, h->ks, h->scal, G, h->kq, h->part);
+                s.x(k_fcg_direction<2>, nbd, CBX * CBY, L64, (const double*)h->kz, (const double*)h->ks,
+                    (const double*)h->scal, G, h->kq, h->part);
             } else {
                 const ColGrid G = zgrid(d0.nx, d0.ny, d0.nz, false, &nbd);
-                k_fcg_direction<1><<<nbd, CBX * CBY, 0, s>>>(L64, h->kz, h->ks, h->scal, G, h->kq, h->part);
+                s.x(k_fcg_direction<1>, nbd, CBX * CBY, L64, (const double*)h->kz, (const double*)h->ks,
+                    (const double*)h->scal, G, h->kq, h->part);
             }
             finish(h, nbd, 12);
         }
         {
             Prof pf(h, MG_K_KRYLOV, 40.0 * N);
-            k_fcg_update<<<lin_grid(d0.ncell()), 256, 0, s>>>(h->kz, h->ks, S.p, h->scal, d0.ncell());
+            s.x(k_fcg_update, lin_grid(d0.ncell()).x, 256, (const double*)h->kz, h->ks, S.p, (const double*)h->scal,
+                d0.ncell());
         }
         Prof pf(h, MG_K_KRYLOV, resid_bytes + 8.0 * N);
         nbz = launch_resid<2>(s, L64, S.p, h->bbar, nullptr, nullptr, h->part, h->kr);
@@ -920,7 +926,7 @@ static mg_status launch_iteration_kernels(SolveState& S) {
         const double* shift = h->scal + 5;
         if (!fused_first_sweep(h)) {
             Prof pf(h, MG_K_OTHER, 16.0 * N);
-            k_sub_mean<double><<<g0, blk, 0, s>>>(S.p, h->scal + 5, d0.nx, d0.ny, d0.nz);
+            s.z(k_sub_mean<double>, g0, blk, S.p, (const double*)(h->scal + 5), d0.nx, d0.ny, d0.nz);
             shift = nullptr;
         }
         vcycle(h, H64, 0, shift);
@@ -931,15 +937,15 @@ static mg_status launch_iteration_kernels(SolveState& S) {
         {
             Prof pf(h, MG_K_REFINE, 20.0 * N);
             if ((d0.ncell() & 1) == 0 && ((uintptr_t)S.p & 15) == 0)
-                k_refine_update2<<<(unsigned)((d0.ncell() / 2 + 511) / 512), 512, 0, s>>>(S.p, h->fe[0], h->scal + 8,
-                                                                                     d0.ncell(), h->scal + 5);
+                s.x(k_refine_update2, (unsigned)((d0.ncell() / 2 + 511) / 512), 512, S.p, (const float*)h->fe[0],
+                    (const double*)(h->scal + 8), d0.ncell(), (const double*)(h->scal + 5));
             else
-                k_refine_update<<<lin_grid(d0.ncell()), 256, 0, s>>>(S.p, h->fe[0], h->scal + 8, d0.ncell(),
-                                                                     h->scal + 5);
+                s.x(k_refine_update, lin_grid(d0.ncell()).x, 256, S.p, (const float*)h->fe[0],
+                    (const double*)(h->scal + 8), d0.ncell(), (const double*)(h->scal + 5));
         }
         // r32 of the next step is scaled by a power of two near the RMS of the
         // residual just used (any power of two leaves the FP32 arithmetic unchanged)
-        k_refine_scale<<<1, 64, 0, s>>>(h->scal + 4, N, h->scal + 8);
+        s.x(k_refine_scale, 1, 64, (const double*)(h->scal + 4), N, h->scal + 8);
         Prof pf(h, MG_K_REFINE, resid_bytes + 4.0 * N);
         nbz = launch_resid<1>(s, L64, S.p, h->bbar, h->scal + 9, h->frhs[0], h->part);
     }
@@ -953,24 +959,18 @@ mg_status solve_launch_iteration(SolveState& S) {
     hipStream_t s = h->stream;
     if (h->o.graph && !h->o.profile && !S.graph_failed) {
         if (!S.gexec) {
-            // record this iteration's launches once; on any failure fall back to eager launches
-            bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
-            if (ok) {
-                const mg_status r = launch_iteration_kernels(S);
-                hipGraph_t g = nullptr;
-                const bool ended = hipStreamEndCapture(s, &g) == hipSuccess;
-                ok = r == MG_OK && ended && g != nullptr;
-                if (ok) {
-                    S.graph = g;
-                    ok = hipGraphInstantiate(&S.gexec, g, nullptr, nullptr, 0) == hipSuccess;
-                } else if (g) {
-                    (void)hipGraphDestroy(g);
-                }
-            }
-            if (!ok) {
+            // record this iteration's launches once and build the graph from them (no
+            // stream capture); on any failure fall back to direct launches
+            S.rec = std::make_shared<Recording>();
+            h->rec = S.rec.get();
+            const mg_status r = launch_iteration_kernels(S);
+            h->rec = nullptr;
+            if (r != MG_OK || build_graph(*S.rec, &S.graph, &S.gexec) != hipSuccess) {
                 (void)hipGetLastError();
                 S.graph_failed = true;
+                S.graph = nullptr;
                 S.gexec = nullptr;
+                S.rec.reset();
             }
         }
         if (S.gexec) {
@@ -1009,6 +1009,7 @@ void solve_release(SolveState& S) {
     if (S.graph) (void)hipGraphDestroy(S.graph);
     S.gexec = nullptr;
     S.graph = nullptr;
+    S.rec.reset();
 }
 
 // Step 4: final mean-zero projection of p (sum(p) from the last residual pass),
@@ -1019,11 +1020,11 @@ void solve_end(SolveState& S, mg_stats* st) {
         const LevelDims& d0 = h->L.d[0];
         Prof pf(h, MG_K_OTHER, 16.0 * d0.ncell());
         if ((d0.ncell() & 1) == 0 && ((uintptr_t)S.p & 15) == 0)
-            k_sub_mean2<<<(unsigned)((d0.ncell() / 2 + 511) / 512), 512, 0, h->stream>>>(S.p, h->scal + 5,
-                                                                                    d0.ncell());
+            launcher(h).x(k_sub_mean2, (unsigned)((d0.ncell() / 2 + 511) / 512), 512, S.p,
+                          (const double*)(h->scal + 5), d0.ncell());
         else
-            k_sub_mean<double><<<col_grid(d0.nx, d0.ny, d0.nz), dim3(BX, BY), 0, h->stream>>>(
-                S.p, h->scal + 5, d0.nx, d0.ny, d0.nz);
+            launcher(h).z(k_sub_mean<double>, col_grid(d0.nx, d0.ny, d0.nz), dim3(BX, BY), S.p,
+                          (const double*)(h->scal + 5), d0.nx, d0.ny, d0.nz);
         S.project = false;
     }
     (void)hipStreamSynchronize(h->stream);

@@ -33,6 +33,7 @@ struct Lvl {
     const T* fx;  // lower x-face of each cell
     const T* fy;  // lower y-face
     const T* fz;  // lower z-face
+    __device__ __forceinline__ Lvl rebased(uintptr_t off) const { return {nx, ny, nz, rb(fx, off), rb(fy, off), rb(fz, off)}; }
 };
 
 // The six face coefficients of cell (i,j,k) at index c, in the order x-, x+,
@@ -142,12 +143,13 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
 }
 
 __device__ __forceinline__ int flat_tid() { return threadIdx.y * blockDim.x + threadIdx.x; }
-__device__ __forceinline__ int flat_bid() {
-    return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-}
+// Flat index within its problem of a column-grid block whose z index within the
+// problem is kz.
+__device__ __forceinline__ int flat_bid(int kz) { return (kz * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x; }
 
-// 2-D block (BX x BY) variant writing two partial sums per block.
-__device__ __forceinline__ void block_partials2(double a, double b, double* __restrict__ part) {
+// 2-D block (BX x BY) variant writing two partial sums per block; bid is the
+// block's index within its problem.
+__device__ __forceinline__ void block_partials2(double a, double b, double* __restrict__ part, int bid) {
     __shared__ double sa[BX * BY / 64], sb[BX * BY / 64];
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_down(a, off, 64);
@@ -159,7 +161,6 @@ __device__ __forceinline__ void block_partials2(double a, double b, double* __re
     if (t == 0) {
         double ta = 0, tb = 0;
         for (int w = 0; w < BX * BY / 64; w++) { ta += sa[w]; tb += sb[w]; }
-        const int bid = flat_bid();
         part[2 * bid] = ta;
         part[2 * bid + 1] = tb;
     }
@@ -171,8 +172,13 @@ __device__ __forceinline__ void block_partials2(double a, double b, double* __re
 // (k_finish2 then adds the workgroups' results), so a large sum is spread over
 // the chip instead of one CU.
 __global__ void __launch_bounds__(FIN_THREADS) k_finish2_part(const double* __restrict__ part, int nblk, int per,
-                                                              double* __restrict__ out) {
-    const int lo = blockIdx.x * per, hi = min(nblk, lo + per);
+                                                              double* __restrict__ out, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    part = rb(part, off_);
+    out = rb(out, off_);
+    const int lo = bid_ * per, hi = min(nblk, lo + per);
     double a = 0, b = 0;
     for (int t = lo + (int)threadIdx.x; t < hi; t += FIN_THREADS) {
         a += part[2 * t];
@@ -180,13 +186,18 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finish2_part(const double* __re
     }
     block_sum2<FIN_THREADS>(a, b);
     if (threadIdx.x == 0) {
-        out[2 * blockIdx.x] = a;
-        out[2 * blockIdx.x + 1] = b;
+        out[2 * bid_] = a;
+        out[2 * bid_ + 1] = b;
     }
 }
 
 __global__ void __launch_bounds__(FIN_THREADS) k_finish2(const double* __restrict__ part, int nblk,
-                                                         double* __restrict__ out) {
+                                                         double* __restrict__ out, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    part = rb(part, off_);
+    out = rb(out, off_);
     double a = 0, b = 0;
     for (int t = threadIdx.x; t < nblk; t += FIN_THREADS) {
         a += part[2 * t];
@@ -199,53 +210,74 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finish2(const double* __restric
 // Partial sums of x and x^2 over the cells (column grid, k strided by gridDim.z).
 template <class T>
 __global__ void __launch_bounds__(BX* BY) k_sum_sq(const T* __restrict__ x, int nx, int ny, int nz,
-                                                  double* __restrict__ part) {
+                                                  double* __restrict__ part, Bt bt) {
+    int kz_, nkz_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.z, gridDim.z, kz_, nkz_, off_)) return;
+    x = rb(x, off_);
+    part = rb(part, off_);
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     double a = 0, b = 0;
     if (i < nx && j < ny)
-        for (int k = blockIdx.z; k < nz; k += gridDim.z) {
+        for (int k = kz_; k < nz; k += nkz_) {
             double v = (double)x[cidx(i, j, k, nx, ny)];
             a += v;
             b += v * v;
         }
-    block_partials2(a, b, part);
+    block_partials2(a, b, part, flat_bid(kz_));
 }
 
 // y = x - sum/n (sum read from device memory); partial sums of y and y^2.
 __global__ void __launch_bounds__(BX* BY) k_project(const double* __restrict__ x, double* __restrict__ y,
                                                    const double* __restrict__ sum, int nx, int ny, int nz,
-                                                   double* __restrict__ part) {
+                                                   double* __restrict__ part, Bt bt) {
+    int kz_, nkz_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.z, gridDim.z, kz_, nkz_, off_)) return;
+    x = rb(x, off_);
+    y = rb(y, off_);
+    sum = rb(sum, off_);
+    part = rb(part, off_);
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     const double mean = sum[0] / ((double)nx * ny * nz);
     double a = 0, b = 0;
     if (i < nx && j < ny)
-        for (int k = blockIdx.z; k < nz; k += gridDim.z) {
+        for (int k = kz_; k < nz; k += nkz_) {
             size_t c = cidx(i, j, k, nx, ny);
             double v = x[c] - mean;
             y[c] = v;
             a += v;
             b += v * v;
         }
-    block_partials2(a, b, part);
+    block_partials2(a, b, part, flat_bid(kz_));
 }
 
 // x -= sum/n (sum from device memory).
 template <class T>
 __global__ void __launch_bounds__(BX* BY) k_sub_mean(T* __restrict__ x, const double* __restrict__ sum,
-                                                    int nx, int ny, int nz) {
+                                                    int nx, int ny, int nz, Bt bt) {
+    int kz_, nkz_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.z, gridDim.z, kz_, nkz_, off_)) return;
+    x = rb(x, off_);
+    sum = rb(sum, off_);
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     if (i >= nx || j >= ny) return;
     const double mean = sum[0] / ((double)nx * ny * nz);
-    for (int k = blockIdx.z; k < nz; k += gridDim.z) {
+    for (int k = kz_; k < nz; k += nkz_) {
         size_t c = cidx(i, j, k, nx, ny);
         x[c] = (T)((double)x[c] - mean);
     }
 }
 
 template <class T>
-__global__ void k_fill(T* __restrict__ x, size_t n, T v) {
-    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; t < n; t += (size_t)gridDim.x * blockDim.x) x[t] = v;
+__global__ void k_fill(T* __restrict__ x, size_t n, T v, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    x = rb(x, off_);
+    size_t t = (size_t)bid_ * blockDim.x + threadIdx.x;
+    for (; t < n; t += (size_t)nb_ * blockDim.x) x[t] = v;
 }
 
 __global__ void k_cast_d2f(const double* __restrict__ x, float* __restrict__ y, size_t n) {
@@ -257,8 +289,13 @@ __global__ void k_cast_d2f(const double* __restrict__ x, float* __restrict__ y, 
 // two at or below the RMS of the residual whose sum of squares is sumsq[0]
 // (1 for a zero residual); out[0] = s, out[1] = 1/s (both exact).  Any power of
 // two gives the same FP32 arithmetic up to that scale.
-__global__ void k_refine_scale(const double* __restrict__ sumsq, double n, double* __restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+__global__ void k_refine_scale(const double* __restrict__ sumsq, double n, double* __restrict__ out, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    sumsq = rb(sumsq, off_);
+    out = rb(out, off_);
+    if (threadIdx.x == 0 && bid_ == 0) {
         const double rms = sqrt(sumsq[0] / n);
         double s = 1.0;
         if (rms > 0.0 && rms < 1e300) s = ldexp(1.0, ilogb(rms));
@@ -440,10 +477,16 @@ __global__ void __launch_bounds__(FIN_THREADS) k_coarse_invert(Lvl<double> L, do
 // p_c = (s - b_c) / d.  Column grid, k strided by gridDim.z.
 template <class T>
 __global__ void __launch_bounds__(BX* BY) k_rb_half(Lvl<T> L, T* __restrict__ p, const T* __restrict__ b,
-                                                   int colour, T omega) {
+                                                   int colour, T omega, Bt bt) {
+    int kz_, nkz_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.z, gridDim.z, kz_, nkz_, off_)) return;
+    L = L.rebased(off_);
+    p = rb(p, off_);
+    b = rb(b, off_);
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     if (i >= L.nx || j >= L.ny) return;
-    for (int k = blockIdx.z; k < L.nz; k += gridDim.z) {
+    for (int k = kz_; k < L.nz; k += nkz_) {
         if (((i + j + k) & 1) != colour) continue;
         T s, d;
         nbsum(L, p, i, j, k, s, d);
@@ -460,11 +503,16 @@ __global__ void __launch_bounds__(BX* BY) k_rb_half(Lvl<T> L, T* __restrict__ p,
 // trilinear interpolation.  One thread per coarse cell; r is the level's
 // residual (stored by the residual kernel).
 template <class T>
-__global__ void k_restrict64(const T* __restrict__ r, int nx, int ny, int nz, T* __restrict__ rc) {
+__global__ void k_restrict64(const T* __restrict__ r, int nx, int ny, int nz, T* __restrict__ rc, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    r = rb(r, off_);
+    rc = rb(rc, off_);
     const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
     const size_t nc = (size_t)cx * cy * cz;
     const double w[4] = {0.125, 0.375, 0.375, 0.125};
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nc; t += (size_t)gridDim.x * blockDim.x) {
+    for (size_t t = (size_t)bid_ * blockDim.x + threadIdx.x; t < nc; t += (size_t)nb_ * blockDim.x) {
         const int I = (int)(t % cx);
         const size_t q = t / cx;
         const int J = (int)(q % cy), K = (int)(q / cy);
@@ -495,7 +543,13 @@ __global__ void k_restrict64(const T* __restrict__ r, int nx, int ny, int nz, T*
 constexpr int GMRES_MAX_M = 16;
 template <class T>
 __global__ void __launch_bounds__(512) k_coarse_gmres(Lvl<double> L, const T* __restrict__ rin, T* __restrict__ eout,
-                                                     int m, double tol, int maxit) {
+                                                     int m, double tol, int maxit, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    L = L.rebased(off_);
+    rin = rb(rin, off_);
+    eout = rb(eout, off_);
     __shared__ double V[GMRES_MAX_M + 1][512];
     __shared__ double H[(GMRES_MAX_M + 1) * GMRES_MAX_M];
     __shared__ double cs[GMRES_MAX_M], sn[GMRES_MAX_M], g[GMRES_MAX_M + 1], y[GMRES_MAX_M];
@@ -532,9 +586,9 @@ __global__ void __launch_bounds__(512) k_coarse_gmres(Lvl<double> L, const T* __
         const double s = stencil_sum(w0, w1, w2, w3, w4, w5, x[nw], x[ne], x[ns], x[nn], x[nd], x[nu]);
         return fma(-diag, x[t], s);
     };
-    const double bt = act ? (double)rin[t] : 0.0;
-    const double mb = bsum(bt) / n;
-    const double bb = act ? bt - mb : 0.0;
+    const double rt = act ? (double)rin[t] : 0.0;
+    const double mb = bsum(rt) / n;
+    const double bb = act ? rt - mb : 0.0;
     const double nb = sqrt(bsum(bb * bb));
     double x = 0.0, r = bb, beta = nb;
     int it = 0;
@@ -600,7 +654,13 @@ __global__ void __launch_bounds__(512) k_coarse_gmres(Lvl<double> L, const T* __
 // Every workgroup forms the mean of r itself.
 template <class T>
 __global__ void __launch_bounds__(512) k_coarse_solve(const double* __restrict__ Binv, int n,
-                                                     const T* __restrict__ r, T* __restrict__ e) {
+                                                     const T* __restrict__ r, T* __restrict__ e, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    Binv = rb(Binv, off_);
+    r = rb(r, off_);
+    e = rb(e, off_);
     __shared__ double rs[512];
     __shared__ double red[8];
     const int t = threadIdx.x;
@@ -614,7 +674,7 @@ __global__ void __launch_bounds__(512) k_coarse_solve(const double* __restrict__
     const double mean = tot / n;
     if (t < n) rs[t] = v - mean;
     __syncthreads();
-    const int lane = t % 64, row = blockIdx.x * 8 + t / 64;
+    const int lane = t % 64, row = bid_ * 8 + t / 64;
     if (row >= n) return;   // whole wavefronts
     double acc = 0;
     for (int c = lane; c < n; c += 64) acc += Binv[(size_t)row * n + c] * rs[c];
@@ -729,7 +789,16 @@ template <class T, int TX, int TY, int NSW, bool RES = false, bool SOR = false>
 __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES ? 2 : 0)))
     k_rb_sweep(Lvl<T> L, const T* __restrict__ pin, T* __restrict__ pout, const T* __restrict__ b, int c0, int kc,
                int tiles_x, int tiles_y, const double* __restrict__ shift_sum, double n_cells, int zero_in,
-               T* __restrict__ rc, T omega) {
+               T* __restrict__ rc, T omega, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    L = L.rebased(off_);
+    pin = rb(pin, off_);
+    pout = rb(pout, off_);
+    b = rb(b, off_);
+    shift_sum = rb(shift_sum, off_);
+    rc = rb(rc, off_);
     using V = typename Vec2<T>::type;
     constexpr int R = 2 * NSW;                  // number of colour stages
     constexpr int E = RES ? 1 : 0;              // extra ring for the residual's neighbours
@@ -752,7 +821,7 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
     constexpr int NP = (NV + NT - 1) / NT;      // staged pairs per thread
     __shared__ __align__(16) T sp[NS * PL];
     const int nx = L.nx, ny = L.ny, nz = L.nz;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = xcd_tile(bid_, nb_);
     const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, chunk = tile / (tiles_x * tiles_y);
     const int i0 = tx * TX, j0 = ty * TY;
     const int k0 = chunk * kc, k1 = min(nz, k0 + kc);
@@ -1108,8 +1177,18 @@ template <class T, int MODE>
 __global__ void __launch_bounds__(CBX* CBY) k_resid_col(Lvl<T> L, const T* __restrict__ p, const T* __restrict__ b,
                                                        ColGrid G, const double* __restrict__ scal_inv_s,
                                                        float* __restrict__ r32, double* __restrict__ part,
-                                                       T* __restrict__ r64) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+                                                       T* __restrict__ r64, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    L = L.rebased(off_);
+    p = rb(p, off_);
+    b = rb(b, off_);
+    scal_inv_s = rb(scal_inv_s, off_);
+    r32 = rb(r32, off_);
+    part = rb(part, off_);
+    r64 = rb(r64, off_);
+    const int tile = xcd_tile(bid_, nb_);
     const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
     const int i = tx * CBX + (int)(threadIdx.x % CBX), j = ty * CBY + (int)(threadIdx.x / CBX);
     const int nx = L.nx, ny = L.ny, nz = L.nz;
@@ -1170,8 +1249,18 @@ template <int MODE>
 __global__ void __launch_bounds__(RES_FLAT_THREADS)
     k_resid_flat(Lvl<double> L, const double* __restrict__ p, const double* __restrict__ b, uint32_t units,
                  const double* __restrict__ scal_inv_s, float* __restrict__ r32, double* __restrict__ part,
-                 double* __restrict__ r64) {
-    const uint32_t t = blockIdx.x * RES_FLAT_THREADS + threadIdx.x;
+                 double* __restrict__ r64, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    L = L.rebased(off_);
+    p = rb(p, off_);
+    b = rb(b, off_);
+    scal_inv_s = rb(scal_inv_s, off_);
+    r32 = rb(r32, off_);
+    part = rb(part, off_);
+    r64 = rb(r64, off_);
+    const uint32_t t = (uint32_t)bid_ * RES_FLAT_THREADS + threadIdx.x;
     double a = 0, q = 0;
     if (t < units) {
         const int nx = L.nx, ny = L.ny, nz = L.nz;
@@ -1216,8 +1305,8 @@ __global__ void __launch_bounds__(RES_FLAT_THREADS)
     if (threadIdx.x == 0) {
         double ta = 0, tb = 0;
         for (int w = 0; w < RES_FLAT_THREADS / 64; w++) { ta += sa[w]; tb += sb[w]; }
-        part[2 * blockIdx.x] = ta;
-        part[2 * blockIdx.x + 1] = tb;
+        part[2 * bid_] = ta;
+        part[2 * bid_ + 1] = tb;
     }
 }
 
@@ -1340,8 +1429,18 @@ __global__ void __launch_bounds__(CBX* CBY) k_resid_cells(Lvl<T> L, const T* __r
                                                          const T* __restrict__ b, ColGrid G,
                                                          const double* __restrict__ scal_inv_s,
                                                          float* __restrict__ r32, double* __restrict__ part,
-                                                         T* __restrict__ r64) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+                                                         T* __restrict__ r64, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    L = L.rebased(off_);
+    p = rb(p, off_);
+    b = rb(b, off_);
+    scal_inv_s = rb(scal_inv_s, off_);
+    r32 = rb(r32, off_);
+    part = rb(part, off_);
+    r64 = rb(r64, off_);
+    const int tile = xcd_tile(bid_, nb_);
     const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
     const int I = tx * CBX + (int)(threadIdx.x % CBX), j = ty * CBY + (int)(threadIdx.x / CBX);
     const int nx = L.nx, ny = L.ny, nz = L.nz;
@@ -1404,11 +1503,18 @@ __global__ void __launch_bounds__(CBX* CBY) k_resid_cells(Lvl<T> L, const T* __r
 template <class T, int NC>
 __global__ void __launch_bounds__(CBX* CBY) k_resid_restrict_cells(Lvl<T> L, const T* __restrict__ p,
                                                                   const T* __restrict__ b, ColGrid G,
-                                                                  T* __restrict__ rc) {
+                                                                  T* __restrict__ rc, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    L = L.rebased(off_);
+    p = rb(p, off_);
+    b = rb(b, off_);
+    rc = rb(rc, off_);
     static_assert(CBY % 2 == 0, "row pairs");
     constexpr int NQ = NC / 2;   // coarse columns per thread
     __shared__ T part[CBY][NQ][CBX];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = xcd_tile(bid_, nb_);
     const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int cnx = nx / 2, cny = ny / 2;
@@ -1473,9 +1579,15 @@ __global__ void __launch_bounds__(CBX* CBY) k_resid_restrict_cells(Lvl<T> L, con
 // counts coarse planes.
 template <class T>
 __global__ void __launch_bounds__(CBX* CBY) k_prolong_col(const T* __restrict__ ec, const T* __restrict__ ac,
-                                                         int cnx, int cny, int cnz, ColGrid G, T* __restrict__ ef) {
+                                                         int cnx, int cny, int cnz, ColGrid G, T* __restrict__ ef, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    ec = rb(ec, off_);
+    ac = rb(ac, off_);
+    ef = rb(ef, off_);
     using V = typename Vec2<T>::type;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = xcd_tile(bid_, nb_);
     const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
     const int nx = 2 * cnx, ny = 2 * cny;
     const int I = tx * CBX + (int)(threadIdx.x % CBX), j = ty * CBY + (int)(threadIdx.x / CBX);
@@ -1570,10 +1682,17 @@ __global__ void __launch_bounds__(CBX* CBY) k_prolong_col(const T* __restrict__ 
 // mean-zero projection of the previous iterate, folded into this pass) and s
 // = scal_s[0] the scale the residual was divided by.
 __global__ void k_refine_update(double* __restrict__ p, const float* __restrict__ e, const double* __restrict__ scal_s,
-                                size_t n, const double* __restrict__ shift_sum) {
+                                size_t n, const double* __restrict__ shift_sum, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    p = rb(p, off_);
+    e = rb(e, off_);
+    scal_s = rb(scal_s, off_);
+    shift_sum = rb(shift_sum, off_);
     const double c = shift_sum[0] / (double)n;
     const double s = scal_s[0];
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+    for (size_t t = (size_t)bid_ * blockDim.x + threadIdx.x; t < n; t += (size_t)nb_ * blockDim.x)
         p[t] = (p[t] - c) + s * (double)e[t];
 }
 
@@ -1581,8 +1700,15 @@ __global__ void k_refine_update(double* __restrict__ p, const float* __restrict_
 // threads per workgroup: the streaming form that measured fastest here.
 __global__ void __launch_bounds__(512) k_refine_update2(double* __restrict__ p, const float* __restrict__ e,
                                                         const double* __restrict__ scal_s, size_t n,
-                                                        const double* __restrict__ shift_sum) {
-    const size_t t = (size_t)blockIdx.x * 512 + threadIdx.x;
+                                                        const double* __restrict__ shift_sum, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    p = rb(p, off_);
+    e = rb(e, off_);
+    scal_s = rb(scal_s, off_);
+    shift_sum = rb(shift_sum, off_);
+    const size_t t = (size_t)bid_ * 512 + threadIdx.x;
     if (2 * t >= n) return;
     const double c = shift_sum[0] / (double)n;
     const double s = scal_s[0];
@@ -1594,14 +1720,43 @@ __global__ void __launch_bounds__(512) k_refine_update2(double* __restrict__ p, 
 }
 
 // p -= sum/n for n values (n even, p 16-byte aligned), one thread per pair.
-__global__ void __launch_bounds__(512) k_sub_mean2(double* __restrict__ p, const double* __restrict__ sum, size_t n) {
-    const size_t t = (size_t)blockIdx.x * 512 + threadIdx.x;
+__global__ void __launch_bounds__(512) k_sub_mean2(double* __restrict__ p, const double* __restrict__ sum, size_t n, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    p = rb(p, off_);
+    sum = rb(sum, off_);
+    const size_t t = (size_t)bid_ * 512 + threadIdx.x;
     if (2 * t >= n) return;
     const double mean = sum[0] / (double)n;
     double2 v = *reinterpret_cast<const double2*>(p + 2 * t);
     v.x = v.x - mean;
     v.y = v.y - mean;
     *reinterpret_cast<double2*>(p + 2 * t) = v;
+}
+
+// dst = src for n values (the device-to-device copy inside a cycle, as a kernel
+// so that a cycle holds kernels only).
+template <class T>
+__global__ void k_copy(T* __restrict__ dst, const T* __restrict__ src, size_t n, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    dst = rb(dst, off_);
+    src = rb(src, off_);
+    for (size_t t = (size_t)bid_ * blockDim.x + threadIdx.x; t < n; t += (size_t)nb_ * blockDim.x) dst[t] = src[t];
+}
+
+// out[2 s], out[2 s + 1] = the problem's scalars src[0], src[1], for the problem
+// of slot s (slot 0 for a single problem); out is an address, not an offset.
+// One block of one wavefront per problem.
+__global__ void k_gather2(const double* __restrict__ src, double* __restrict__ out, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    const int slot = bt.base ? (int)blockIdx.x / bt.per : 0;
+    src = rb(src, off_);
+    if (threadIdx.x < 2) out[2 * slot + threadIdx.x] = src[threadIdx.x];
 }
 
 // ---------------------------------------------------------------- Krylov acceleration
@@ -1616,21 +1771,32 @@ __global__ void __launch_bounds__(512) k_sub_mean2(double* __restrict__ p, const
 // Partial sums of z.q and r.z over the cells (column grid, k strided by gridDim.z).
 __global__ void __launch_bounds__(BX* BY) k_fcg_dots(const double* __restrict__ z, const double* __restrict__ q,
                                                     const double* __restrict__ r, int nx, int ny, int nz,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part, Bt bt) {
+    int kz_, nkz_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.z, gridDim.z, kz_, nkz_, off_)) return;
+    z = rb(z, off_);
+    q = rb(q, off_);
+    r = rb(r, off_);
+    part = rb(part, off_);
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     double a = 0, b = 0;
     if (i < nx && j < ny)
-        for (int k = blockIdx.z; k < nz; k += gridDim.z) {
+        for (int k = kz_; k < nz; k += nkz_) {
             const size_t c = cidx(i, j, k, nx, ny);
             a += z[c] * q[c];
             b += r[c] * z[c];
         }
-    block_partials2(a, b, part);
+    block_partials2(a, b, part, flat_bid(kz_));
 }
 
 // beta = -(z.q) / (s.q) with the previous direction's s.q; 0 before the first
 // direction (s.q is reset to 0 when a solve starts).
-__global__ void k_fcg_beta(double* __restrict__ scal) {
+__global__ void k_fcg_beta(double* __restrict__ scal, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    scal = rb(scal, off_);
     if (threadIdx.x == 0) {
         const double sq = scal[12];
         scal[14] = sq == 0.0 ? 0.0 : -scal[10] / sq;
@@ -1665,8 +1831,17 @@ template <int NC>
 __global__ void __launch_bounds__(CBX* CBY) k_fcg_direction(Lvl<double> L, const double* __restrict__ z,
                                                            const double* __restrict__ so,
                                                            const double* __restrict__ scal, ColGrid G,
-                                                           double* __restrict__ q, double* __restrict__ part) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+                                                           double* __restrict__ q, double* __restrict__ part, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    L = L.rebased(off_);
+    z = rb(z, off_);
+    so = rb(so, off_);
+    scal = rb(scal, off_);
+    q = rb(q, off_);
+    part = rb(part, off_);
+    const int tile = xcd_tile(bid_, nb_);
     const int tx = tile % G.tiles_x, ty = (tile / G.tiles_x) % G.tiles_y, chunk = tile / (G.tiles_x * G.tiles_y);
     const int I = tx * CBX + (int)(threadIdx.x % CBX), j = ty * CBY + (int)(threadIdx.x / CBX);
     const int nx = L.nx, ny = L.ny, nz = L.nz;
@@ -1711,10 +1886,17 @@ __global__ void __launch_bounds__(CBX* CBY) k_fcg_direction(Lvl<double> L, const
 
 // s = z + beta s_old (stored), p += alpha s with alpha = (r.z) / (s.q).
 __global__ void k_fcg_update(const double* __restrict__ z, double* __restrict__ s, double* __restrict__ p,
-                             const double* __restrict__ scal, size_t n) {
+                             const double* __restrict__ scal, size_t n, Bt bt) {
+    int bid_, nb_;
+    uintptr_t off_;
+    if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
+    z = rb(z, off_);
+    s = rb(s, off_);
+    p = rb(p, off_);
+    scal = rb(scal, off_);
     const double beta = scal[14], alpha = scal[11] / scal[12];
-    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    size_t t = (size_t)bid_ * blockDim.x + threadIdx.x;
+    for (; t < n; t += (size_t)nb_ * blockDim.x) {
         const double sv = fma(beta, s[t], z[t]);
         s[t] = sv;
         p[t] = fma(alpha, sv, p[t]);
