@@ -214,6 +214,33 @@ mg_status mg_solve(mg_handle *h, const double *rhs, double *p, double tol, mg_st
 /* Release host-side state.  The workspace belongs to the caller.  NULL is ignored. */
 void mg_destroy(mg_handle *h);
 
+/*
+ * For callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): mg_setup followed by mg_solve
+ * on one coefficient field, with the workspace taken from a device array of
+ * MG_STATIC_WORKSPACE_BYTES inside the library instead of the caller.  The call
+ * makes no device or pinned allocation (no hipMalloc, hipFree, hipHostMalloc,
+ * graph or event); each GPU the library runs on holds its own copy of the array
+ * from the first call on it until the process ends.  Grids whose workspace
+ * (mg_workspace_bytes) exceeds MG_STATIC_WORKSPACE_BYTES are refused: every grid
+ * up to 128^3 fits in both precisions.
+ * Arguments and results as mg_setup and mg_solve (g, o, faces, bc; rhs, p, tol,
+ * st); stream must belong to the current device.  options.profile and
+ * options.graph are ignored (both would allocate); smoother variants come from
+ * the tuning cache of earlier setups of the same grid size, else one fixed
+ * variant (every variant gives bit-identical results).  Blocking on return.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (two host threads, or streams the caller has not ordered) race and give
+ * undefined results.  Nothing in the array needs to survive between calls; each
+ * call initialises what it reads.
+ * Errors: those of mg_setup and mg_solve; MG_E_WORKSPACE for a grid larger than
+ * the static workspace (nothing is launched).
+ */
+#define MG_STATIC_WORKSPACE_BYTES (160u * 1024u * 1024u)
+mg_status mg_solve_static(const mg_grid *g, const mg_options *o, const double *bx, const double *by,
+                          const double *bz, mg_bc bc, const double *rhs, double *p, double tol, mg_stats *st,
+                          void *stream);
+
 /* Hierarchy inspection (for tests): number of levels and dims of level l. */
 mg_status mg_level_dims(const mg_handle *h, int l, int *nx, int *ny, int *nz);
 

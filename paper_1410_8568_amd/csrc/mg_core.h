@@ -73,6 +73,9 @@ struct mg_handle {
     const uintptr_t* bt_base = nullptr;
     int bt_slots = 1;
     mgrt::Recording* rec = nullptr;
+    // no allocation anywhere (static workspace): smoother variants come from the
+    // tuning cache or a fixed default instead of timed trials
+    bool no_alloc = false;
     double* host = nullptr;  // pinned host copy of device scalars
     int tile[MG_MAX_LEVELS];   // smoother variant per level
     int rtile[MG_MAX_LEVELS];  // variant of the fused pre-smoothing + restriction pass (0: none)

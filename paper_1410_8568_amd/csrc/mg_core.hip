@@ -545,6 +545,12 @@ void tune_store_locked(const std::array<int, 4>& k, int v, int rv) {
 }
 }  // namespace
 
+// Variant used without timing (no-allocation setups on grid sizes not tuned
+// before): the two-sweep 64x8 tile with about 256 workgroups, which has a fused
+// pre-smoothing + restriction pass in both precisions.  Every variant gives
+// bit-identical results; only the speed differs.
+constexpr int UNTUNED_VARIANT = 16;
+
 template <class T>
 static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b, T* rc, int* choice,
                             int* rchoice) {
@@ -559,6 +565,11 @@ static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b
             *rchoice = h->o.nu1 == 2 ? it->second.second : 0;
             return MG_OK;
         }
+    }
+    if (h->no_alloc) {   // timing needs events and scratch fills: use the fixed variant
+        *choice = UNTUNED_VARIANT;
+        *rchoice = h->o.nu1 == 2 && has_restrict_variant<T>(UNTUNED_VARIANT) ? UNTUNED_VARIANT : 0;
+        return MG_OK;
     }
     hipStream_t s = h->stream;
     Launcher ls;

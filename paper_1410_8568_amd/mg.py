@@ -31,8 +31,9 @@ EXPORTS = [
     "mg_default_options", "mg_workspace_bytes", "mg_setup", "mg_solve", "mg_destroy",
     "mg_level_dims", "mg_level_tile", "mg_copy_level", "mg_server_create", "mg_batch_submit", "mg_poll",
     "mg_server_destroy", "mg_status_string", "mg_last_error", "mg_divergence", "mg_correct_velocity",
-    "mg_project", "mg_faces_from_levelset",
+    "mg_project", "mg_faces_from_levelset", "mg_solve_static",
 ]
+MG_STATIC_WORKSPACE_BYTES = 160 * 1024 * 1024
 
 
 class Grid(ctypes.Structure):
@@ -117,6 +118,8 @@ def lib():
     L.mg_correct_velocity.argtypes = [vp, vp, d, vp, vp, vp, vp]
     L.mg_project.argtypes = [vp, vp, vp, vp, d, d, vp, vp, d, ctypes.POINTER(Stats), vp]
     L.mg_faces_from_levelset.argtypes = [ctypes.POINTER(Grid), vp, d, d, d, i, vp, vp, vp, vp]
+    L.mg_solve_static.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Options), vp, vp, vp, i, vp, vp, d,
+                                  ctypes.POINTER(Stats), vp]
     L.mg_status_string.argtypes = [i]
     L.mg_status_string.restype = ctypes.c_char_p
     L.mg_last_error.argtypes = []
@@ -226,6 +229,29 @@ def faces_from_levelset(phi, rho_l, rho_g, eps, faces="arith", out=None, stream=
                                       _ptr(out[1]), _ptr(out[2]), _stream(stream))
     if rc != MG_OK:
         raise MGError(rc, "mg_faces_from_levelset")
+    return out
+
+
+def solve_static(bx, by, bz, b, p, tol=1e-10, precision="fp64", stream=None, check=True, **kw):
+    """Setup and solve of one field in the library's static device workspace
+    (``mg_solve_static``: no allocation by the library; grids up to 128^3).
+    p is in/out as in ``Solver.solve``.  Returns the stats dict with "rc"."""
+    nz, ny, nxp = bx.shape
+    n = (nxp - 1, ny, nz)
+    nx = n[0]
+    _check_field(bx, (nz, ny, nx + 1), "bx")
+    _check_field(by, (nz, ny + 1, nx), "by")
+    _check_field(bz, (nz + 1, ny, nx), "bz")
+    _check_field(b, (nz, ny, nx), "b")
+    _check_field(p, (nz, ny, nx), "p")
+    o = options(precision=precision, **kw)
+    st = Stats()
+    rc = lib().mg_solve_static(ctypes.byref(Grid(*n)), ctypes.byref(o), _ptr(bx), _ptr(by), _ptr(bz), MG_BC_NEUMANN,
+                               _ptr(b), _ptr(p), ctypes.c_double(tol), ctypes.byref(st), _stream(stream))
+    if check and rc != MG_OK:
+        raise MGError(rc, "mg_solve_static")
+    out = st.to_dict()
+    out["rc"] = rc
     return out
 
 

@@ -137,3 +137,30 @@ def test_bench_traffic_figure_is_tied_to_workload_and_kernel_code(tmp_path, monk
     assert bench.traffic_for("smooth_fine", 512) == 3.0e9
     src.write_text("int f() { return 2; }\n")
     assert bench.traffic_for("smooth_fine", 512) is None
+
+
+def test_static_solve_refuses_before_any_device_call():
+    """mg_solve_static validates on the host first: null arrays, a bad bc, an
+    unaligned p, and a grid whose workspace exceeds the static array (160^3 in
+    FP32-refined mode) are refused without touching the device (the pointers
+    below are never dereferenced)."""
+    from paper_1410_8568_amd import mg
+    L = mg.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    st = mg.Stats()
+
+    def call(n, opts, bc=mg.MG_BC_NEUMANN, p=fake):
+        return L.mg_solve_static(ctypes.byref(mg.Grid(*n)), ctypes.byref(opts), fake, fake, fake, bc, fake, p,
+                                 ctypes.c_double(1e-10), ctypes.byref(st), None)
+
+    o = mg.options(precision="fp32_refined")
+    assert L.mg_solve_static(None, None, None, None, None, 0, None, None, ctypes.c_double(1e-10), None,
+                             None) == mg.MG_E_INVALID
+    assert call((32, 32, 32), o, bc=7) == mg.MG_E_INVALID
+    assert call((32, 32, 32), o, p=ctypes.c_void_p((1 << 20) + 8)) == mg.MG_E_INVALID
+    assert mg.workspace_bytes((160, 160, 160), o) > mg.MG_STATIC_WORKSPACE_BYTES
+    assert call((160, 160, 160), o) == mg.MG_E_WORKSPACE
+    assert b"static workspace" in L.mg_last_error()
+    for n in ((128, 128, 128),):
+        for prec in ("fp64", "fp32_refined"):
+            assert mg.workspace_bytes(n, mg.options(precision=prec, n_coarsest=8)) <= mg.MG_STATIC_WORKSPACE_BYTES
