@@ -413,7 +413,7 @@ def batch_bench(args):
     torch.cuda.synchronize()
     seq_s = time.perf_counter() - t
     o = mg.options(precision=prec)
-    arena = sum(mg.workspace_bytes(P.n, o) for P in probs) + (1 << 20)
+    arena = sum(mg.server_request_bytes(P.n, o) for P in probs) + (1 << 20)
     srv = mg.Server(arena, precision=prec, max_slots=args.slots)
     outs = [torch.zeros_like(b) for (_, _, _, b) in dev]
     torch.cuda.synchronize()

@@ -374,17 +374,41 @@ typedef struct {
     double submit_ms, start_ms, finish_ms;   /* server clock */
 } mg_result;
 
+typedef struct {
+    int classes;                  /* size classes seen (one per distinct grid) */
+    int graphs;                   /* iteration graphs built (one per class and batch capacity) */
+    long long replays;            /* graph replays (one outer iteration of a whole class each) */
+    long long problem_iterations; /* outer iterations summed over problems (members per replay) */
+    int max_batch;                /* most problems advanced by one replay */
+    int resident;                 /* problems resident now */
+    long long completed;          /* requests finished (any status) */
+} mg_server_info;
+
+/*
+ * Arena bytes one request of grid g takes in a server whose solver options are
+ * o: its workspace (mg_workspace_bytes) plus a copy of p (8 bytes per cell), the
+ * server iterating on the copy so that all of a problem's arrays share one
+ * layout, rounded up to 256 bytes.  Pure; no device call.  Errors: as
+ * mg_workspace_bytes.
+ */
+mg_status mg_server_request_bytes(const mg_grid *g, const mg_options *o, size_t *bytes);
+
 /*
  * Create a server that keeps each admitted request's hierarchy resident in
  * `arena` (caller-owned device memory of arena_bytes, 256-byte aligned; the HBM
  * budget; it must outlive the server).  A scheduler thread admits requests in
- * arrival order as soon as their workspace (mg_workspace_bytes) fits in the free
- * part of the arena (first fit) and a slot is free, builds their hierarchy in
- * place, and advances every resident problem one iteration (a V-cycle, or an
- * outer refinement iteration) at a time on its slot's stream, relaunching each
- * as soon as its previous iteration completes; finished problems release their
- * memory at once, and waiting requests take their place.  The same request gives
- * the same result alone or in any mix.  Errors: MG_E_INVALID, MG_E_HIP.
+ * arrival order as soon as fewer than max_slots are resident and their footprint
+ * (mg_server_request_bytes) fits in the free part of the arena (first fit), and
+ * builds their hierarchy in place.  Requests of one grid size form a size class
+ * that advances together: each replay of the class's HIP graph is one outer
+ * iteration (a V-cycle, or the inner FP32 V-cycles and the FP64 refinement step)
+ * of every resident problem of the class, each kernel launch covering all of
+ * them (the batched execution of Sec. 2.3's cycle for same-size problems); one
+ * graph is built per size class and batch capacity (a power of two).  Converged
+ * problems leave at once and release their memory; waiting requests join at the
+ * next replay.  Classes run on the given streams (class k on streams[k mod
+ * nstreams]) and overlap on the device.  The same request gives the same result
+ * alone (mg_solve) or in any mix, bit for bit.  Errors: MG_E_INVALID, MG_E_HIP.
  */
 mg_status mg_server_create(void *arena, size_t arena_bytes, const mg_server_options *o,
                            mg_server **out);
@@ -407,6 +431,9 @@ mg_status mg_batch_submit(mg_server *s, const mg_request *r, uint64_t *ticket);
  * forgotten.  Thread-safe.  Errors: MG_E_NOT_FOUND.
  */
 mg_status mg_poll(mg_server *s, uint64_t ticket, mg_result *out);
+
+/* Counters of the server's batched execution (a snapshot).  Errors: MG_E_INVALID. */
+mg_status mg_server_stats(mg_server *s, mg_server_info *out);
 
 /* Stop the scheduler after finishing all queued work, then free host state. */
 void mg_server_destroy(mg_server *s);

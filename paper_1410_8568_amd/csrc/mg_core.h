@@ -37,13 +37,16 @@ struct Layout {
     size_t fe[MG_MAX_LEVELS], frhs[MG_MAX_LEVELS];                // FP32 levels (refined mode)
     size_t bbar = 0, binv = 0, scal = 0, part = 0, flag = 0;
     size_t kr = 0, kz = 0, ks = 0, kq = 0;                         // Krylov vectors (level 0, FP64)
+    size_t pw = 0;                                                 // the server's copy of p (0: none)
     int ncoarse = 0;
     int max_blocks = 0;
     size_t total = 0;
 };
 
-// Validates the grid/options and fills the layout.  Returns MG_OK or MG_E_INVALID.
-mg_status plan(const mg_grid* g, const mg_options* o, Layout* L);
+// Validates the grid/options and fills the layout.  with_p: also room for a copy
+// of p (the solve server iterates on it, so that every array of a problem lies
+// in its workspace).  Returns MG_OK or MG_E_INVALID.
+mg_status plan(const mg_grid* g, const mg_options* o, Layout* L, bool with_p = false);
 
 dim3 col_grid(int nx, int ny, int nz);
 
@@ -67,12 +70,14 @@ struct mg_handle {
     double* part = nullptr;
     int* flag = nullptr;
     double *kr = nullptr, *kz = nullptr, *ks = nullptr, *kq = nullptr;   // Krylov: r, z, s, q
+    double* pw = nullptr;   // the workspace copy of p (server), if planned
     hipStream_t stream = nullptr;
     // batch context of the cycle launches (one problem: base == nullptr, nslots == 1)
     // and, while a graph is being built, the recording that receives them
     const uintptr_t* bt_base = nullptr;
     int bt_slots = 1;
     mgrt::Recording* rec = nullptr;
+    int launch_failed = 0;   // set by a launch the batch geometry does not allow
     // no allocation anywhere (static workspace): smoother variants come from the
     // tuning cache or a fixed default instead of timed trials
     bool no_alloc = false;
@@ -93,12 +98,13 @@ struct mg_handle {
 
 namespace mgrt {
 // The launcher of a handle's cycle kernels: its stream, batch context and recording.
-inline Launcher launcher(const mg_handle* h) {
+inline Launcher launcher(mg_handle* h) {
     Launcher l;
     l.stream = h->stream;
     l.base = h->bt_base;
     l.nslots = h->bt_slots;
     l.rec = h->rec;
+    l.failed = &h->launch_failed;
     return l;
 }
 
@@ -148,6 +154,15 @@ mg_status solve_launch_iteration(SolveState& S);  // asynchronous: one (outer) i
 mg_status launch_iteration_kernels(SolveState& S);
 void solve_after_sync(SolveState& S);             // after h->stream is synchronised
 bool solve_running(const SolveState& S);
-void solve_end(SolveState& S, mg_stats* st);
+void solve_end(SolveState& S, mg_stats* st);        // solve_end_launch, synchronise, solve_end_finish
+void solve_end_launch(SolveState& S);                // asynchronous: the final mean-zero projection of p
+void solve_end_finish(SolveState& S, mg_stats* st);  // after the stream has passed solve_end_launch
+// The residual sums of the last iteration (sum r^2, sum p) of every problem of
+// the handle's launcher into out[2 s], out[2 s + 1] (s: the batch slot; 0 for one
+// problem); out is a device address.
+void launch_gather(mg_handle* h, double* out);
+// Handle arrays bound to the workspace base h->ws (which may be a stand-in base
+// for a batch's offset pointers).
+void bind(mg_handle* h);
 void solve_release(SolveState& S);                // frees the captured graph (error paths)
 }  // namespace mgrt

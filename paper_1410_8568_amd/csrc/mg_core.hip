@@ -81,7 +81,7 @@ static bool resid_flat_fits(const LevelDims& d) {
     return (d.nx & 1) == 0 && (size_t)d.nx * d.ny <= (size_t)512 * 512;
 }
 
-mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
+mg_status plan(const mg_grid* g, const mg_options* o, Layout* L, bool with_p) {
     if (!g || !o || !L) {
         set_error("null argument");
         return MG_E_INVALID;
@@ -174,6 +174,7 @@ mg_status plan(const mg_grid* g, const mg_options* o, Layout* L) {
         L->ks = take(L->d[0].ncell() * 8);
         L->kq = take(L->d[0].ncell() * 8);
     }
+    if (with_p) L->pw = take(L->d[0].ncell() * 8);
     L->binv = take((size_t)L->ncoarse * L->ncoarse * 8);
     L->scal = take(64 * 8);
     int mb = 0;
@@ -248,7 +249,7 @@ static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b
 template <class T>
 static bool has_restrict_variant(int v);
 
-static void bind(mg_handle* h) {
+void bind(mg_handle* h) {
     const Layout& L = h->L;
     char* w = h->ws;
     const bool f32 = h->o.precision == MG_FP32_REFINED;
@@ -282,6 +283,7 @@ static void bind(mg_handle* h) {
     h->kz = kry ? (double*)(w + L.kz) : nullptr;
     h->ks = kry ? (double*)(w + L.ks) : nullptr;
     h->kq = kry ? (double*)(w + L.kq) : nullptr;
+    h->pw = L.pw ? (double*)(w + L.pw) : nullptr;
 }
 
 mg_status setup_launch(mg_handle* h, const double* bx, const double* by, const double* bz) {
@@ -962,7 +964,16 @@ mg_status launch_iteration_kernels(SolveState& S) {
     }
     finish(h, nbz, 4);
     HIPCHK(hipGetLastError());
+    if (h->launch_failed) {
+        h->launch_failed = 0;
+        set_error("a column-grid launch of this batch would exceed the grid's z limit");
+        return MG_E_HIP;
+    }
     return MG_OK;
+}
+
+void launch_gather(mg_handle* h, double* out) {
+    launcher(h).x(k_gather2, 1, 64, (const double*)(h->scal + 4), out);
 }
 
 mg_status solve_launch_iteration(SolveState& S) {
@@ -1024,8 +1035,9 @@ void solve_release(SolveState& S) {
 }
 
 // Step 4: final mean-zero projection of p (sum(p) from the last residual pass),
-// then statistics.  Blocking.
-void solve_end(SolveState& S, mg_stats* st) {
+// enqueued (solve_end_launch); then statistics (solve_end_finish, once the stream
+// has passed it).  solve_end does both, blocking.
+void solve_end_launch(SolveState& S) {
     mg_handle* h = S.h;
     if (S.project) {
         const LevelDims& d0 = h->L.d[0];
@@ -1038,7 +1050,10 @@ void solve_end(SolveState& S, mg_stats* st) {
                           (const double*)(h->scal + 5), d0.nx, d0.ny, d0.nz);
         S.project = false;
     }
-    (void)hipStreamSynchronize(h->stream);
+}
+
+void solve_end_finish(SolveState& S, mg_stats* st) {
+    mg_handle* h = S.h;
     solve_release(S);
     S.st.outer = S.it;
     if (h->o.precision == MG_FP64) S.st.cycles = S.it;
@@ -1053,6 +1068,12 @@ void solve_end(SolveState& S, mg_stats* st) {
     }
     S.st.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - S.t0).count();
     if (st) *st = S.st;
+}
+
+void solve_end(SolveState& S, mg_stats* st) {
+    solve_end_launch(S);
+    (void)hipStreamSynchronize(S.h->stream);
+    solve_end_finish(S, st);
 }
 
 mg_status solve_impl(mg_handle* h, const double* rhs, double* p, double tol, mg_stats* st) {

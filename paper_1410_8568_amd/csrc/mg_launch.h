@@ -49,9 +49,17 @@ struct Launcher {
         go(k, dim3(nblk * (unsigned)nslots), dim3(nthr), nblk, std::forward<A>(a)...);
     }
     // Column grid g of blocks b per problem (the slot is the z block index / g.z).
+    // A batch whose z extent would pass kMaxGridZ is neither launched nor recorded:
+    // *failed is set instead (the caller turns it into an error).
+    static constexpr unsigned long long kMaxGridZ = 65535;
+    int* failed = nullptr;
     template <class... P, class... A>
     void z(void (*k)(P...), dim3 g, dim3 b, A&&... a) const {
         const unsigned per = g.z;
+        if ((unsigned long long)per * (unsigned long long)nslots > kMaxGridZ) {
+            if (failed) *failed = 1;
+            return;
+        }
         g.z *= (unsigned)nslots;
         go(k, g, b, per, std::forward<A>(a)...);
     }

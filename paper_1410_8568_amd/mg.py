@@ -31,7 +31,7 @@ EXPORTS = [
     "mg_default_options", "mg_workspace_bytes", "mg_setup", "mg_solve", "mg_destroy",
     "mg_level_dims", "mg_level_tile", "mg_copy_level", "mg_server_create", "mg_batch_submit", "mg_poll",
     "mg_server_destroy", "mg_status_string", "mg_last_error", "mg_divergence", "mg_correct_velocity",
-    "mg_project", "mg_faces_from_levelset", "mg_solve_static",
+    "mg_project", "mg_faces_from_levelset", "mg_solve_static", "mg_server_request_bytes", "mg_server_stats",
 ]
 MG_STATIC_WORKSPACE_BYTES = 160 * 1024 * 1024
 
@@ -82,6 +82,12 @@ class Request(ctypes.Structure):
                 ("tol", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("classes", ctypes.c_int), ("graphs", ctypes.c_int), ("replays", ctypes.c_longlong),
+                ("problem_iterations", ctypes.c_longlong), ("max_batch", ctypes.c_int), ("resident", ctypes.c_int),
+                ("completed", ctypes.c_longlong)]
+
+
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("stats", Stats), ("submit_ms", ctypes.c_double),
                 ("start_ms", ctypes.c_double), ("finish_ms", ctypes.c_double)]
@@ -112,6 +118,8 @@ def lib():
     L.mg_server_create.argtypes = [vp, sz, ctypes.POINTER(ServerOptions), ctypes.POINTER(vp)]
     L.mg_batch_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
     L.mg_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Result)]
+    L.mg_server_request_bytes.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Options), ctypes.POINTER(sz)]
+    L.mg_server_stats.argtypes = [vp, ctypes.POINTER(ServerInfo)]
     L.mg_server_destroy.argtypes = [vp]
     L.mg_server_destroy.restype = None
     L.mg_divergence.argtypes = [ctypes.POINTER(Grid), vp, vp, vp, d, vp, vp]
@@ -165,6 +173,15 @@ def workspace_bytes(n, opts: Options) -> int:
     st = lib().mg_workspace_bytes(ctypes.byref(g), ctypes.byref(opts), ctypes.byref(out))
     if st != MG_OK:
         raise MGError(st, "mg_workspace_bytes")
+    return out.value
+
+
+def server_request_bytes(n, opts: Options) -> int:
+    """Arena bytes one request of grid n takes in a server with solver options opts."""
+    out = ctypes.c_size_t(0)
+    st = lib().mg_server_request_bytes(ctypes.byref(Grid(*n)), ctypes.byref(opts), ctypes.byref(out))
+    if st != MG_OK:
+        raise MGError(st, "mg_server_request_bytes")
     return out.value
 
 
@@ -431,6 +448,15 @@ class Server:
         self._keep.pop(ticket, None)
         return dict(rc=st, stats=res.stats.to_dict(), submit_ms=res.submit_ms, start_ms=res.start_ms,
                     finish_ms=res.finish_ms)
+
+    def stats(self):
+        """Counters of the batched execution: classes, graphs, replays, problem_iterations,
+        max_batch, resident, completed."""
+        info = ServerInfo()
+        st = lib().mg_server_stats(self.h, ctypes.byref(info))
+        if st != MG_OK:
+            raise MGError(st, "mg_server_stats")
+        return {k: getattr(info, k) for k, _ in ServerInfo._fields_}
 
     def wait(self, ticket, timeout_s=120.0):
         import time

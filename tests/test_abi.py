@@ -164,3 +164,17 @@ def test_static_solve_refuses_before_any_device_call():
     for n in ((128, 128, 128),):
         for prec in ("fp64", "fp32_refined"):
             assert mg.workspace_bytes(n, mg.options(precision=prec, n_coarsest=8)) <= mg.MG_STATIC_WORKSPACE_BYTES
+
+
+def test_server_request_bytes_is_workspace_plus_a_copy_of_p():
+    from paper_1410_8568_amd import mg
+    for n in ((32, 32, 32), (40, 24, 12), (64, 64, 64)):
+        for prec in ("fp64", "fp32_refined"):
+            o = mg.options(precision=prec)
+            w = mg.workspace_bytes(n, o)
+            r = mg.server_request_bytes(n, o)
+            cells = n[0] * n[1] * n[2]
+            assert w + 8 * cells <= r <= w + 8 * cells + 512 and r % 256 == 0
+    with pytest.raises(mg.MGError):
+        mg.server_request_bytes((9, 9, 9), mg.options())
+    assert mg.lib().mg_server_stats(None, None) == mg.MG_E_INVALID

@@ -40,7 +40,7 @@ def test_mix_equals_alone(precision):
         S.close()
     # budget for about three of the largest at once, so the mix queues for memory
     o = mg.options(precision=precision)
-    need = [mg.workspace_bytes(P.n, o) for P in probs]
+    need = [mg.server_request_bytes(P.n, o) for P in probs]
     srv = mg.Server(3 * max(need) + 4096, precision=precision, max_slots=4)
     outs, tickets = [], []
     for rep in range(2):
@@ -68,7 +68,7 @@ def test_budget_and_errors():
     from paper_1410_8568_amd import mg
     P = inputs.config0()
     bx, by, bz, b = mg.to_device(P)
-    need = mg.workspace_bytes(P.n, mg.options())
+    need = mg.server_request_bytes(P.n, mg.options())
     srv = mg.Server(need + 1024, max_slots=8)   # room for one request at a time
     with pytest.raises(mg.MGError) as ei:
         big = inputs.sphere_problem(64)
@@ -136,3 +136,48 @@ def test_submit_waits_for_producer_stream(nstreams):
         assert res["rc"] == 0, res
         assert res["stats"]["history"] == ref_st["history"], q
         assert torch.equal(p, ref_p), q
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_size_classes_run_batched(precision):
+    """Problems of one grid size advance together: each replay of a size class's
+    graph is one outer iteration of all of its resident problems, every launch
+    covering all of them.  Five 32^3, six 64^3 and three 128^3 problems (uneven
+    scenes, ratios 10-1000) submitted at once: every result equals its alone solve
+    (mg_solve) bit for bit, matches the oracle to 1e-8, and the counters show
+    replays that advanced several problems at once."""
+    import torch
+    from paper_1410_8568_amd import mg
+    probs = (inputs.batch_problems(5, sizes=(32,), seed=51, rhs_seed0=5100)
+             + inputs.batch_problems(6, sizes=(64,), seed=52, rhs_seed0=5200)
+             + inputs.batch_problems(3, sizes=(128,), seed=53, rhs_seed0=5300))
+    dev = [mg.to_device(P) for P in probs]
+    alone = []
+    for (bx, by, bz, b) in dev:
+        S = mg.Solver(bx, by, bz, precision=precision)
+        p = torch.zeros_like(b)
+        st = S.solve(b, p, tol=1e-10)
+        assert st["rc"] == 0
+        alone.append((p.clone(), st))
+        S.close()
+    o = mg.options(precision=precision)
+    arena = sum(mg.server_request_bytes(P.n, o) for P in probs) + (1 << 20)
+    srv = mg.Server(arena, precision=precision, max_slots=16)
+    outs = [torch.zeros_like(b) for (_, _, _, b) in dev]
+    tickets = [srv.submit(bx, by, bz, b, p, tol=1e-10) for (bx, by, bz, b), p in zip(dev, outs)]
+    results = [srv.wait(t) for t in tickets]
+    info = srv.stats()
+    srv.close()
+    print(f"{precision}: {info}", flush=True)
+    for q, (res, p) in enumerate(zip(results, outs)):
+        ref_p, ref_st = alone[q]
+        assert res["rc"] == 0, (q, res)
+        assert res["stats"]["history"] == ref_st["history"], q
+        assert torch.equal(p, ref_p), q
+    assert info["classes"] == 3 and info["completed"] == len(probs) and info["resident"] == 0
+    assert info["max_batch"] >= 5
+    assert info["problem_iterations"] >= 2 * info["replays"]
+    for P, (p, _) in zip(probs, alone):
+        ref = oracle.solve(P.bx, P.by, P.bz, P.b, tol=1e-10, precision=precision)
+        pn = p.cpu().numpy()
+        assert np.linalg.norm(pn - ref["p"]) / np.linalg.norm(ref["p"]) <= 1e-8
