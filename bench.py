@@ -421,6 +421,7 @@ def batch_bench(args):
     tickets = [srv.submit(bx, by, bz, b, p, tol=args.tol) for (bx, by, bz, b), p in zip(dev, outs)]
     res = [srv.wait(tk) for tk in tickets]
     srv_s = time.perf_counter() - t
+    info = srv.stats()
     srv.close()
     bad = [r["rc"] for r in res if r["rc"] != 0]
     lat = sorted(r["finish_ms"] - r["submit_ms"] for r in res)
@@ -434,59 +435,77 @@ def batch_bench(args):
         "server_s": srv_s, "sequential_s": seq_s, "speedup_vs_sequential": seq_s / srv_s,
         "cell_updates_per_s": seq_cycles / srv_s, "failed": len(bad),
         "latency_ms_p50": lat[len(lat) // 2], "latency_ms_max": lat[-1],
+        "server_batching": info,
     }
     print(json.dumps(out), flush=True)
 
 
 def serve_bench(args):
     """Open-loop Poisson arrivals of solves with n ~ U{64,128,192,256} and batch-like
-    geometry; p50/p99 latency (submit to finish) and achieved solves/s per rate."""
+    geometry; p50/p99 latency (submit to finish) and achieved solves/s per rate.
+
+    Each request's face coefficients are built on the device from its scene's level
+    set (mg_faces_from_levelset: indicator, eq. 8, face means) on a producer
+    stream at arrival, and the request is submitted on that stream (the server
+    starts on it after the face build); --faces host submits faces built on the
+    host beforehand instead."""
     import numpy as np
     import torch
     from paper_1410_8568_amd import inputs, mg
     prec = "fp32_refined"
     rates = [float(r) for r in args.rates.split(",")]
-    # a pool of distinct fields per size class (requests reuse the pool's fields)
+    # a pool of distinct scenes per size class (requests reuse the pool's scenes):
+    # the level set, density ratio and rhs on the device
     pool = {}
     t = time.perf_counter()
     for i, d in enumerate(inputs.request_stream(4 * args.pool, 1.0)):
-        if len(pool.setdefault(d[1]["n"], [])) < args.pool:
-            pool[d[1]["n"]].append(mg.to_device(inputs.problem_from_desc(d[1])))
+        desc = d[1]
+        if len(pool.setdefault(desc["n"], [])) < args.pool:
+            P = inputs.problem_from_desc(desc)
+            dv = mg.to_device(P)
+            phi = torch.from_numpy(inputs.scene_levelset(desc)).cuda()
+            pool[desc["n"]].append(dict(faces=dv[:3], b=dv[3], phi=phi, ratio=desc["ratio"]))
     log(f"generated request pool {[(n, len(v)) for n, v in sorted(pool.items())]} in {time.perf_counter() - t:.1f} s")
     for n, v in pool.items():
-        mg.Solver(*v[0][:3], precision=prec).close()   # warm the tuner cache
-    o = mg.options(precision=prec)
+        mg.Solver(*v[0]["faces"], precision=prec).close()   # warm the tuner cache
     arena = int(args.arena_gb * (1 << 30))
+    prod = torch.cuda.Stream()
     lines = []
     for rate in rates:
         stream = inputs.request_stream(args.requests, rate, seed=4)
         srv = mg.Server(arena, precision=prec, max_slots=args.slots)
-        outs = {}
         tickets = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i, (ta, d) in enumerate(stream):
             while time.perf_counter() - t0 < ta:
                 time.sleep(0.0001)
-            bx, by, bz, b = pool[d["n"]][i % len(pool[d["n"]])]
-            p = torch.zeros_like(b)
-            outs[i] = p
-            tickets.append((i, srv.submit(bx, by, bz, b, p, tol=args.tol)))
+            e = pool[d["n"]][i % len(pool[d["n"]])]
+            n = d["n"]
+            with torch.cuda.stream(prod):
+                p = torch.zeros_like(e["b"])
+                if args.faces == "device":
+                    faces = mg.faces_from_levelset(e["phi"], e["ratio"], 1.0, 1.5 / n, stream=prod)
+                else:
+                    faces = e["faces"]
+                tickets.append((i, srv.submit(*faces, e["b"], p, tol=args.tol, stream=prod)))
         res = [srv.wait(tk, timeout_s=600) for _, tk in tickets]
         span = time.perf_counter() - t0
+        info = srv.stats()
         srv.close()
         lat = np.array([r["finish_ms"] - r["submit_ms"] for r in res])
         line = {"rate_per_s": rate, "requests": len(res), "solves_per_s": len(res) / span,
                 "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
-                "failed": int(sum(r["rc"] != 0 for r in res))}
+                "failed": int(sum(r["rc"] != 0 for r in res)), "max_batch": info["max_batch"],
+                "problems_per_replay": info["problem_iterations"] / max(1, info["replays"])}
         log(json.dumps(line))
         lines.append(line)
     out = {"metric": "serving: p50/p99 latency and solves/s under Poisson arrivals (FP32-refined)",
            "value": lines[-1]["solves_per_s"], "unit": "solves/s", "higher_is_better": True, "n_gpus": 1,
            "data": "synthetic",
            "config": {"workload": f"n~U{{64,128,192,256}}, batch-like geometry, {args.requests} requests per rate, "
-                                  f"pool of {args.pool} fields per size", "arena_gb": args.arena_gb,
-                      "slots": args.slots},
+                                  f"pool of {args.pool} scenes per size, faces built on the {args.faces}",
+                      "arena_gb": args.arena_gb, "slots": args.slots},
            "rates": lines}
     print(json.dumps(out), flush=True)
 
@@ -526,6 +545,8 @@ def main():
     ap.add_argument("--pool", type=int, default=2)
     ap.add_argument("--arena-gb", type=float, default=24.0)
     ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--faces", choices=["device", "host"], default="device",
+                    help="serving: build each request's faces on the device from its level set, or on the host")
     args = ap.parse_args()
     if args.traffic:
         write_traffic(*args.traffic, n=args.n)

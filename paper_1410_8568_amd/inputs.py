@@ -32,7 +32,7 @@ __all__ = [
     "Problem", "smoothed_heaviside", "cell_centres", "faces_from_alpha",
     "divergence_rhs", "velocity_field", "normal_rhs", "drop_splash_levelset", "sphere_problem", "drop_splash_problem",
     "config0", "config1", "config2", "batch_problems", "request_stream",
-    "layered_problem", "layered_profile", "constant_problem",
+    "layered_problem", "layered_profile", "constant_problem", "scene_levelset",
 ]
 
 
@@ -281,6 +281,16 @@ def scene_problem(n, depth, ratio, drops, rhs_seed, faces="arith") -> Problem:
     return Problem(dims, bx, by, bz, b,
                    dict(kind="scene", n=n, film=depth, drops=drops, ratio=ratio,
                         seed=rhs_seed))
+
+
+def scene_levelset(desc):
+    """The level set phi [n][n][n] (signed distance of the union of the film and the
+    drops, positive in the liquid) of a scene description from ``batch_problems``
+    or ``request_stream``, for building its properties on the device; with the
+    half-width 1.5/n and the description's density ratio it gives the faces of
+    ``problem_from_desc(desc)``."""
+    n = desc["n"]
+    return _geometry_phi((n, n, n), desc["drops"], desc["film"])(cell_centres(n))
 
 
 def batch_problems(count=64, sizes=(32, 64, 96, 128), seed=3, rhs_seed0=3000,

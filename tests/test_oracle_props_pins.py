@@ -62,3 +62,16 @@ def test_matches_the_host_generator(faces):
     for g, ref in zip(got, (P.bx, P.by, P.bz)):
         assert np.array_equal(g == 0, ref == 0)
         assert np.max(np.abs(g - ref)) <= 1e-13 * np.abs(ref).max()
+
+
+def test_scene_levelset_gives_the_scene_faces():
+    """The level set of a random scene (the serving workload), turned into faces by
+    the oracle's level-set route with the scene's ratio and half-width 1.5/n, gives
+    the faces the host generator builds for the same scene."""
+    import oracle
+    from paper_1410_8568_amd import inputs
+    for t, d in inputs.request_stream(3, 1.0, sizes=(24, 32)):
+        P = inputs.problem_from_desc(d)
+        fx, fy, fz = oracle.faces_from_levelset(inputs.scene_levelset(d), d["ratio"], 1.0, 1.5 / d["n"])
+        for a, b in ((fx, P.bx), (fy, P.by), (fz, P.bz)):
+            assert np.allclose(a, b, rtol=2e-14, atol=0)
