@@ -61,7 +61,8 @@ struct Job {
     mg_handle* h = nullptr;        // the problem's own handle (its workspace, real addresses)
     SolveState S;
     hipEvent_t ready = nullptr;    // recorded on the caller's stream at submit
-    hipEvent_t ev = nullptr;       // end of the problem's own start or end work
+    int res = -1;                  // resident slot: its pinned scalar block and event
+    hipEvent_t ev = nullptr;       // end of the problem's own start or end work (the slot's event)
     Class* cls = nullptr;
     int slot = -1;                 // batch slot while it iterates
     JobState state = QUEUED;
@@ -104,6 +105,12 @@ struct mg_server {
     std::deque<Job*> queue;
     std::unordered_map<uint64_t, Job*> jobs;
     int resident = 0;                        // admitted and not yet complete
+    // per resident slot, allocated once (pinned allocations and their frees would
+    // synchronise the device on every request): a pinned block for the problem's
+    // scalars and an event
+    double* host_blocks = nullptr;           // [max_slots][16]
+    std::vector<hipEvent_t> res_events;
+    std::vector<int> res_free;               // free resident slot indices
     std::vector<Job*> starting, ending;      // scheduler thread only
     std::map<std::array<int, 3>, Class*> classes;
     std::vector<hipStream_t> streams;        // class c runs on streams[c % streams.size()]
@@ -168,19 +175,19 @@ Class* class_for(mg_server* sv, const mg_grid& g) {
 void complete(mg_server* sv, Job* j, int status, bool sync) {
     if (sync && j->cls) (void)hipStreamSynchronize(j->cls->stream);
     solve_release(j->S);
-    if (j->ev) {
-        (void)hipEventDestroy(j->ev);
-        j->ev = nullptr;
-    }
+    j->ev = nullptr;
     std::lock_guard<std::mutex> lk(sv->mu);
     j->result.status = status;
     j->result.finish_ms = sv->now_ms();
     j->state = DONE;
     if (j->h) {
+        j->h->host = nullptr;   // the slot's pinned block stays with the server
         mg_destroy(j->h);
         j->h = nullptr;
     }
     sv->alloc.release(j->off, j->bytes);
+    sv->res_free.push_back(j->res);
+    j->res = -1;
     sv->resident--;
     sv->info.completed++;
 }
@@ -204,14 +211,10 @@ bool start_job(mg_server* sv, Job* j) {
     plan(&h->g, &h->o, &h->L, true);
     h->ws = sv->arena + j->off;
     h->stream = c->stream;
+    h->host = sv->host_blocks + 16 * (size_t)j->res;
     j->h = h;
-    if (hipHostMalloc((void**)&h->host, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        h->host = nullptr;
-        complete(sv, j, MG_E_HIP, false);
-        return false;
-    }
-    if (hipEventCreateWithFlags(&j->ev, hipEventDisableTiming) != hipSuccess ||
-        hipStreamWaitEvent(c->stream, j->ready, 0) != hipSuccess) {
+    j->ev = sv->res_events[j->res];
+    if (hipStreamWaitEvent(c->stream, j->ready, 0) != hipSuccess) {
         complete(sv, j, MG_E_HIP, false);
         return false;
     }
@@ -407,12 +410,14 @@ void scheduler(mg_server* sv) {
                 sv->cv.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
                 if (sv->stop && sv->queue.empty() && idle(sv)) return;
             }
-            while (!sv->queue.empty() && sv->resident < sv->o.max_slots) {
+            while (!sv->queue.empty() && !sv->res_free.empty()) {
                 Job* j = sv->queue.front();
                 size_t off;
                 if (!sv->alloc.alloc(j->bytes, &off)) break;
                 sv->queue.pop_front();
                 sv->resident++;
+                j->res = sv->res_free.back();
+                sv->res_free.pop_back();
                 j->off = off;
                 j->state = STARTING;
                 admitted.push_back(j);
@@ -534,6 +539,23 @@ mg_status mg_server_create(void* arena, size_t arena_bytes, const mg_server_opti
                 sv->streams.push_back(st);
             }
         }
+        if (hipHostMalloc((void**)&sv->host_blocks, (size_t)o->max_slots * 16 * sizeof(double),
+                          hipHostMallocDefault) != hipSuccess) {
+            sv->host_blocks = nullptr;
+            set_error("pinned host allocation failed");
+            mg_server_destroy(sv);
+            return MG_E_HIP;
+        }
+        for (int q = 0; q < o->max_slots; q++) {
+            hipEvent_t ev;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                set_error("event creation failed");
+                mg_server_destroy(sv);
+                return MG_E_HIP;
+            }
+            sv->res_events.push_back(ev);
+            sv->res_free.push_back(o->max_slots - 1 - q);
+        }
         sv->th = std::thread(scheduler, sv);
         *out = sv;
         return MG_OK;
@@ -625,6 +647,8 @@ void mg_server_destroy(mg_server* sv) {
         delete kv.second;
     }
     for (auto& kv : sv->classes) destroy_class(kv.second);
+    for (auto e : sv->res_events) (void)hipEventDestroy(e);
+    if (sv->host_blocks) (void)hipHostFree(sv->host_blocks);
     if (sv->own_streams)
         for (auto x : sv->streams) (void)hipStreamDestroy(x);
     delete sv;
