@@ -65,26 +65,30 @@ def profiled(build, b, p, tol):
     return st
 
 
-def cpu_baseline(P, n_coarsest, outer_needed, precision):
-    """The oracle, timed on the host: hierarchy setup plus one outer iteration of
-    the same solve, scaled to the number of iterations the GPU needed."""
+def cpu_baseline(P, n_coarsest, precision, tol):
+    """The oracle timed on the host: the same solve (precision, tolerance, coarsest
+    grid) of the same input to convergence, from p = 0; the time after the
+    hierarchy setup is reported (the GPU step excludes setup too).  Returns the
+    baseline record and the oracle's solution."""
     import oracle
     oracle.lib()
     t0 = time.perf_counter()
-    its = 4
-    r = oracle.solve(P.bx, P.by, P.bz, P.b, n_coarsest=n_coarsest, max_cycles=its, tol=1e-10,
-                     precision=precision)
+    r = oracle.solve(P.bx, P.by, P.bz, P.b, n_coarsest=n_coarsest, max_cycles=60, tol=tol, precision=precision)
     wall = time.perf_counter() - t0
     setup_s, rest_s = oracle.last_timing()
-    # rest_s = projection + initial residual + `its` iterations with their residuals;
-    # scale the per-iteration time by the GPU's count (the solve step excludes setup)
-    per_it = rest_s / its
-    est_s = per_it * outer_needed
-    return dict(value=est_s * 1e3, unit="ms", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{precision} oracle on the same {P.n[0]}^3 input: {its} outer iterations "
-                       f"({rest_s:.2f} s, after {setup_s:.2f} s of hierarchy setup), per-iteration time "
-                       f"scaled to the {outer_needed} iterations the GPU solve took; "
-                       f"{wall:.1f} s of CPU wall time measured")
+    rec = dict(value=rest_s * 1e3, unit="ms", cores=oracle.num_threads(), kind="oracle",
+               sample=f"{precision} oracle on the same {P.n[0]}^3 input to relative residual {tol:g} "
+                      f"({r['status']}, {r['cycles']} outer iterations, final {r['history'][-1]:.2e}), "
+                      f"measured after {setup_s:.2f} s of hierarchy setup; {wall:.1f} s of CPU wall time in all")
+    return rec, r
+
+
+def oracle_reference(P, n_coarsest):
+    """p*: the oracle's FP64 solve to relative residual 1e-13 (or stagnation)."""
+    import oracle
+    t0 = time.perf_counter()
+    r = oracle.solve(P.bx, P.by, P.bz, P.b, n_coarsest=n_coarsest, max_cycles=60, tol=1e-13)
+    return r, time.perf_counter() - t0
 
 
 # Algorithmic HBM bytes per cell of the two projection kernels (FP64): the
@@ -519,6 +523,9 @@ def main():
     ap.add_argument("--n-coarsest", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tight-tol", type=float, default=1e-11,
+                    help="also time both solvers to this tolerance (0: skip): the one at which the FP32-refined "
+                         "result is within 1e-8 of the FP64 oracle's p* with margin")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--inner-m", type=int, default=0, help="FP32 V-cycles per outer iteration (0: library default)")
     ap.add_argument("--graph", type=int, default=1, help="replay each outer iteration as a HIP graph (1) or launch eagerly (0)")
@@ -616,17 +623,33 @@ def main():
     ms32, wall32, st32 = timed_solves(S32, b, p, args.steps, args.warmup, args.tol)
     last32 = st32[-1]
     p32 = p.clone()
+    host32 = p32.cpu().numpy()
     log(f"fp32_refined: {ms32:.2f} ms/solve, outer {last32['outer']}, rho {last32['rel_residual']:.2e}")
+    tight, tight_host = {}, {}
+    if args.tight_tol > 0:
+        # the tolerance at which the error against the FP64 oracle's p* is well inside 1e-8
+        mst, _, stt = timed_solves(S32, b, p, max(2, args.steps // 4), 1, args.tight_tol)
+        tight["fp32_refined_ms"] = mst
+        tight["fp32_refined_cycles"] = stt[-1]["cycles"]
+        tight_host["fp32_refined_tol_%g" % args.tight_tol] = p.cpu().numpy()
     S32.close()
     prof32 = profiled(lambda profile: build("fp32_refined", profile), b, p, args.tol)
 
     res = {}
+    host64 = None
     if not args.no_fp64:
         S64, setup64 = build("fp64")
         ms64, wall64, st64 = timed_solves(S64, b, p, args.steps, args.warmup, args.tol)
         last64 = st64[-1]
         log(f"fp64: {ms64:.2f} ms/solve, cycles {last64['cycles']}, rho {last64['rel_residual']:.2e}")
         p64 = p.clone()
+        host64 = p64.cpu().numpy()
+        if args.tight_tol > 0:
+            mst, _, stt = timed_solves(S64, b, p, max(2, args.steps // 4), 1, args.tight_tol)
+            tight["fp64_ms"] = mst
+            tight["fp64_cycles"] = stt[-1]["cycles"]
+            tight["speedup_fp32_refined_vs_fp64"] = mst / tight["fp32_refined_ms"]
+            tight_host["fp64_tol_%g" % args.tight_tol] = p.cpu().numpy()
         S64.close()
         prof64 = profiled(lambda profile: build("fp64", profile), b, p, args.tol)
         rel = (torch.linalg.vector_norm(p32 - p64) / torch.linalg.vector_norm(p64)).item()
@@ -715,10 +738,31 @@ def main():
                      "avg_launch_ms": dom_avg_ms, "bytes_per_launch": dom_bytes},
         "kernel_ms_fp32_refined": prof32["kernel_ms"],
     }
+    if tight:
+        tight["tol"] = args.tight_tol
+        out["at_tight_tol"] = tight
     out.update(res)
     if not args.no_cpu_baseline:
+        # the oracle on the host: the baseline (the same FP32-refined solve, measured to
+        # convergence) and p* (FP64 to 1e-13); every GPU result's error against them
+        import numpy as np
+
+        def rel(a, b):
+            return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
         try:
-            out["cpu_baseline"] = cpu_baseline(P, args.n_coarsest, last32["outer"], "fp32_refined")
+            out["cpu_baseline"], r32 = cpu_baseline(P, args.n_coarsest, "fp32_refined", args.tol)
+            log(f"cpu baseline: {out['cpu_baseline']['value']:.0f} ms on {out['cpu_baseline']['cores']} threads")
+            rstar, star_s = oracle_reference(P, args.n_coarsest)
+            log(f"oracle p*: {rstar['cycles']} cycles to {rstar['history'][-1]:.2e} in {star_s:.1f} s")
+            err = {"p_star_rel_residual": float(rstar["history"][-1]), "p_star_cycles": rstar["cycles"],
+                   "fp32_refined_vs_oracle_fp32_refined": rel(host32, r32["p"]),
+                   "fp32_refined_vs_p_star": rel(host32, rstar["p"])}
+            if host64 is not None:
+                err["fp64_vs_p_star"] = rel(host64, rstar["p"])
+            for key, hp in tight_host.items():
+                err[key + "_vs_p_star"] = rel(hp, rstar["p"])
+            out["oracle_error"] = err
         except Exception as e:  # the baseline is a report, never the product path
             out["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
