@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace mgk {
 
 // Map the dispatch order of workgroups onto tiles so that each XCD works on a
@@ -27,9 +29,12 @@ struct Bt {
     int per;
 };
 
+// The shift is applied as byte-pointer arithmetic (not through an integer), so
+// the result keeps the parameter's provenance and no-alias information.
 template <class P>
 __device__ __forceinline__ P* rb(P* p, uintptr_t off) {
-    return p ? (P*)((uintptr_t)p + off) : p;
+    using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+    return p ? reinterpret_cast<P*>(reinterpret_cast<C*>(p) + off) : p;
 }
 
 // Block index and count within the problem along the slot dimension (x of a
