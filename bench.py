@@ -199,9 +199,11 @@ def traffic_for(kernel, n):
         t = json.load(open(TRAFFIC_FILE))
     except Exception:
         return None
-    if t.get("source_sha") != kernel_source_sha() or t.get("class") != kernel or t.get("n") != n:
-        return None
-    return t.get("bytes_per_launch")
+    sha = kernel_source_sha()
+    for e in t.get("entries", [t]):
+        if e.get("source_sha") == sha and e.get("class") == kernel and e.get("n") == n:
+            return e.get("bytes_per_launch")
+    return None
 
 
 def calibrate_copy(gib=1, reps=5):
@@ -271,8 +273,15 @@ def write_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, n, gib=1):
            "fetch_bytes": sum(fetch) / len(fetch), "write_bytes": sum(write) / len(write),
            "bytes_per_launch": (sum(fetch) + sum(write)) / len(fetch), "fetch_scale": fs, "write_scale": ws,
            "source_sha": kernel_source_sha()}
+    # one entry per grid size; entries of other sizes taken on the same kernel code stay
+    try:
+        old = json.load(open(TRAFFIC_FILE))
+        entries = [e for e in old.get("entries", [old])
+                   if e.get("n") != n and e.get("source_sha") == out["source_sha"]]
+    except Exception:
+        entries = []
     with open(TRAFFIC_FILE, "w") as f:
-        json.dump(out, f, indent=1)
+        json.dump({"entries": sorted(entries + [out], key=lambda e: e["n"])}, f, indent=1)
         f.write("\n")
     print(json.dumps(out))
 

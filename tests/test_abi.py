@@ -137,6 +137,14 @@ def test_bench_traffic_figure_is_tied_to_workload_and_kernel_code(tmp_path, monk
     assert bench.traffic_for("smooth_fine", 512) == 3.0e9
     src.write_text("int f() { return 2; }\n")
     assert bench.traffic_for("smooth_fine", 512) is None
+    # one entry per grid size
+    sha = bench.kernel_source_sha()
+    tf.write_text(json.dumps({"entries": [
+        {"class": "smooth_fine", "n": 512, "bytes_per_launch": 3.0e9, "source_sha": sha},
+        {"class": "smooth_fine", "n": 1024, "bytes_per_launch": 2.4e10, "source_sha": sha}]}))
+    assert bench.traffic_for("smooth_fine", 512) == 3.0e9
+    assert bench.traffic_for("smooth_fine", 1024) == 2.4e10
+    assert bench.traffic_for("smooth_fine", 256) is None
 
 
 def test_static_solve_refuses_before_any_device_call():
