@@ -383,7 +383,7 @@ struct Hier {
     const T* a[MG_MAX_LEVELS];
 };
 
-template <class T, int TX, int TY, int NSW, bool RES = false>
+template <class T, int TX, int TY, int NSW, bool RES = false, bool SKIP = false>
 static void launch_sweep(const Launcher& ln, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0, int target,
                          const double* shift_sum, int zero_in, T* rc, double omega) {
     const int gx = (L.nx + TX - 1) / TX, gy = (L.ny + TY - 1) / TY;
@@ -394,7 +394,10 @@ static void launch_sweep(const Launcher& ln, const Lvl<T>& L, const T* pin, T* p
     if (RES && (kc & 1)) kc++;   // the restriction pairs planes 2K, 2K+1 within a chunk
     chunks = (L.nz + kc - 1) / kc;
     constexpr int NT = (TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES ? 2 : 0));
-    if (omega != 1.0)   // successive over-relaxation (a separate instantiation)
+    if constexpr (SKIP)   // Gauss-Seidel only: the caller checked omega == 1
+        ln.x(k_rb_sweep<T, TX, TY, NSW, RES, false, true>, tiles * chunks, NT, L, pin, pout, b, c0, kc, gx, gy,
+             shift_sum, (double)L.nx * L.ny * L.nz, zero_in, rc, T(1));
+    else if (omega != 1.0)   // successive over-relaxation (a separate instantiation)
         ln.x(k_rb_sweep<T, TX, TY, NSW, RES, true>, tiles * chunks, NT, L, pin, pout, b, c0, kc, gx, gy, shift_sum,
              (double)L.nx * L.ny * L.nz, zero_in, rc, (T)omega);
     else
@@ -458,10 +461,25 @@ static bool has_restrict_variant(int v) {
 // Two-sweep pass of variant v that also forms the residual of its result and
 // restricts it into rc (the next level's right-hand side); returns false
 // (nothing launched) when v has no such pass.
+//
+// skip_red: the iterate's red cells already hold what the pass's first (red)
+// stage would compute (the previous cycle's post-smoothing ended with red, and
+// omega == 1), so that stage is left out (bit-identical results; FP32 only).
 template <class T>
 static bool fused_sweep_restrict(const Launcher& s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b,
-                                 const double* shift_sum, int zero_in, T* rc, double omega = 1.0) {
+                                 const double* shift_sum, int zero_in, T* rc, double omega = 1.0,
+                                 bool skip_red = false) {
     const int target = variant_target(v);
+    if constexpr (sizeof(T) == 4) {
+        if (skip_red) {
+            switch ((v - 1) / 3) {
+                case 4: launch_sweep<T, 64, 4, 2, true, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc, 1.0); return true;
+                case 5: launch_sweep<T, 64, 8, 2, true, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc, 1.0); return true;
+                case 7: launch_sweep<T, 64, 16, 2, true, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc, 1.0); return true;
+                default: return false;
+            }
+        }
+    }
     switch ((v - 1) / 3) {
         case 4: launch_sweep<T, 64, 4, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc, omega); return true;
         case 5: launch_sweep<T, 64, 8, 2, true>(s, L, pin, pout, b, 0, target, shift_sum, zero_in, rc, omega); return true;
@@ -685,8 +703,12 @@ static bool fused_first_sweep(const mg_handle* h) {
     return h->L.nlev > 1 && h->tile[0] > 0 && h->o.nu1 >= sweeps_per_pass(h->tile[0]);
 }
 
+// red_done: the level's iterate was last updated by a red half-sweep (the
+// previous cycle's post-smoothing on this level), so a fused pre-smoothing pass
+// may leave out its first (red) stage.
 template <class T>
-static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nullptr, bool zero_init = false) {
+static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nullptr, bool zero_init = false,
+                   bool red_done = false) {
     const Launcher s = launcher(h);
     const LevelDims& d = H.d[l];
     if (l == H.nlev - 1) {
@@ -714,7 +736,7 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
                                    (zero_init ? (double)d.ncell() * sizeof(T) : 0.0);
         Prof pf(h, l == 0 ? MG_K_SMOOTH_FINE : MG_K_SMOOTH, sweep_bytes + restrict_bytes);
         fused_sweep_restrict<T>(s, rtile, H.L[l], cur, alt, H.rhs[l], shift_sum, zero_init ? 1 : 0, H.rhs[l + 1],
-                                h->o.omega);
+                                h->o.omega, red_done && !zero_init && h->o.omega == 1.0);
         std::swap(cur, alt);
     } else if (h->o.restrict64) {
         // residual stored in the (free) ping-pong buffer, then the 64-point restriction
@@ -946,7 +968,10 @@ mg_status launch_iteration_kernels(SolveState& S) {
         Prof pf(h, MG_K_NORM, resid_bytes);
         nbz = launch_resid<0>(s, L64, S.p, h->bbar, nullptr, nullptr, h->part);
     } else {
-        for (int m = 0; m < h->o.inner_m; m++) vcycle(h, H32, 0, nullptr, m == 0);   // e starts from zero
+        // e starts from zero; from the second inner cycle on, the previous cycle's
+        // post-smoothing (nu2 >= 1 sweeps, black then red) has left the red cells
+        // of level 0 exactly where the next pre-smoothing's red half-sweep would put them
+        for (int m = 0; m < h->o.inner_m; m++) vcycle(h, H32, 0, nullptr, m == 0, m > 0 && h->o.nu2 >= 1);
         {
             Prof pf(h, MG_K_REFINE, 20.0 * N);
             if ((d0.ncell() & 1) == 0 && ((uintptr_t)S.p & 15) == 0)

@@ -779,13 +779,20 @@ struct Vec2<double> {
 // loaded two steps ahead, the other faces and b one step ahead, before the
 // compute of the current step.  Requires even nx (every smoothed level has one).
 //
+// SKIP (two-sweep passes, Gauss-Seidel only): the first colour stage is left
+// out.  Valid when every cell of that colour already holds the value the stage
+// would compute, i.e. the iterate was last updated by a half-sweep of that
+// colour (a cycle's post-smoothing ends with the colour the next cycle's
+// pre-smoothing starts with): Gauss-Seidel on one colour given the other is
+// exact, so repeating it reproduces the stored values bit for bit.
+//
 // With shift_sum non-null, every value of pin is first reduced by
 // shift_sum[0] / n_cells (the mean-zero projection of the previous iterate, done
 // on the fly instead of as a separate pass; same arithmetic as k_sub_mean).
 // With zero_in set, the iterate entering the pass is zero and pin is not read:
 // its loads go through a buffer resource of range 0, which returns 0 (a
 // coarse-grid correction's first smoothing pass; no separate fill).
-template <class T, int TX, int TY, int NSW, bool RES = false, bool SOR = false>
+template <class T, int TX, int TY, int NSW, bool RES = false, bool SOR = false, bool SKIP = false>
 __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES ? 2 : 0)))
     k_rb_sweep(Lvl<T> L, const T* __restrict__ pin, T* __restrict__ pout, const T* __restrict__ b, int c0, int kc,
                int tiles_x, int tiles_y, const double* __restrict__ shift_sum, double n_cells, int zero_in,
@@ -801,6 +808,7 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
     rc = rb(rc, off_);
     using V = typename Vec2<T>::type;
     constexpr int R = 2 * NSW;                  // number of colour stages
+    static_assert(!SKIP || (NSW == 2 && !SOR), "the first stage may be skipped in Gauss-Seidel two-sweep passes");
     constexpr int E = RES ? 1 : 0;              // extra ring for the residual's neighbours
     constexpr int RXs = R + 2 * E, RYs = R + E; // staged ring (x: whole pairs)
     constexpr int W = TX + 2 * RXs, H = TY + 2 * RYs, W2 = W / 2;
@@ -998,7 +1006,7 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
             const int ol = e ? opart : opart - 1, orr = e ? opart + 1 : opart;   // x-neighbours
             const int oy = CL ? opart : oc;
             const int os = oy - 2 * HS, on = oy + 2 * HS;             // y-neighbours
-            static_for<1, R + 1>([&](auto hc) {
+            static_for<1 + (SKIP ? 1 : 0), R + 1>([&](auto hc) {
                 constexpr int h = decltype(hc)::value;
                 constexpr int rg = R - h + E;                           // this stage's ring width
                 const int z = t - h + 1;
