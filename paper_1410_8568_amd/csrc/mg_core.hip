@@ -383,9 +383,17 @@ struct Hier {
     const T* a[MG_MAX_LEVELS];
 };
 
-template <class T, int TX, int TY, int NSW, bool RES = false, bool SKIP = false>
+// The FP64 refinement update p <- (p - sum / N) + s * e, fused into the FP32
+// pass that writes the correction e of level 0 in final form.
+struct RefineUpd {
+    double* p;
+    const double* s;     // scale of the FP32 right-hand side
+    const double* sum;   // sum of p (its mean is taken out on the way)
+};
+
+template <class T, int TX, int TY, int NSW, bool RES = false, bool SKIP = false, bool UPD = false>
 static void launch_sweep(const Launcher& ln, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0, int target,
-                         const double* shift_sum, int zero_in, T* rc, double omega) {
+                         const double* shift_sum, int zero_in, T* rc, double omega, const RefineUpd& u = {}) {
     const int gx = (L.nx + TX - 1) / TX, gy = (L.ny + TY - 1) / TY;
     const int tiles = gx * gy;
     // chunks of >= 8 planes, so the redundant planes at chunk ends stay a small fraction
@@ -394,15 +402,19 @@ static void launch_sweep(const Launcher& ln, const Lvl<T>& L, const T* pin, T* p
     if (RES && (kc & 1)) kc++;   // the restriction pairs planes 2K, 2K+1 within a chunk
     chunks = (L.nz + kc - 1) / kc;
     constexpr int NT = (TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES ? 2 : 0));
-    if constexpr (SKIP)   // Gauss-Seidel only: the caller checked omega == 1
+    const double N = (double)L.nx * L.ny * L.nz;
+    if constexpr (UPD)   // FP32 Gauss-Seidel only: the caller checked omega == 1
+        ln.x(k_rb_sweep<T, TX, TY, NSW, false, false, false, true>, tiles * chunks, NT, L, pin, pout, b, c0, kc, gx,
+             gy, shift_sum, N, zero_in, rc, T(1), u.p, u.s, u.sum);
+    else if constexpr (SKIP)   // Gauss-Seidel only: the caller checked omega == 1
         ln.x(k_rb_sweep<T, TX, TY, NSW, RES, false, true>, tiles * chunks, NT, L, pin, pout, b, c0, kc, gx, gy,
-             shift_sum, (double)L.nx * L.ny * L.nz, zero_in, rc, T(1));
+             shift_sum, N, zero_in, rc, T(1), nullptr, nullptr, nullptr);
     else if (omega != 1.0)   // successive over-relaxation (a separate instantiation)
-        ln.x(k_rb_sweep<T, TX, TY, NSW, RES, true>, tiles * chunks, NT, L, pin, pout, b, c0, kc, gx, gy, shift_sum,
-             (double)L.nx * L.ny * L.nz, zero_in, rc, (T)omega);
+        ln.x(k_rb_sweep<T, TX, TY, NSW, RES, true>, tiles * chunks, NT, L, pin, pout, b, c0, kc, gx, gy, shift_sum, N,
+             zero_in, rc, (T)omega, nullptr, nullptr, nullptr);
     else
-        ln.x(k_rb_sweep<T, TX, TY, NSW, RES, false>, tiles * chunks, NT, L, pin, pout, b, c0, kc, gx, gy, shift_sum,
-             (double)L.nx * L.ny * L.nz, zero_in, rc, T(1));
+        ln.x(k_rb_sweep<T, TX, TY, NSW, RES, false>, tiles * chunks, NT, L, pin, pout, b, c0, kc, gx, gy, shift_sum, N,
+             zero_in, rc, T(1), nullptr, nullptr, nullptr);
 }
 
 // Fused variant v (1..MG_NUM_TILES): tile (v - 1) / 3 of the list (four one-sweep
@@ -422,11 +434,30 @@ static bool variant_native(int v) {
     return sizeof(T) == 4 || v <= 18;
 }
 
-// Fused sweep variant v in 1..MG_NUM_TILES: one pass doing sweeps_per_pass(v) sweeps.
+// True when a pass of variant v can apply the refinement update (FP32 two-sweep
+// Gauss-Seidel passes).
+template <class T>
+static bool has_update_variant(int v, double omega) {
+    return sizeof(T) == 4 && v > 12 && omega == 1.0;
+}
+
+// Fused sweep variant v in 1..MG_NUM_TILES: one pass doing sweeps_per_pass(v) sweeps
+// (with u non-null, also the refinement update; has_update_variant(v) must hold).
 template <class T>
 static void fused_sweep(const Launcher& s, int v, const Lvl<T>& L, const T* pin, T* pout, const T* b, int c0,
-                        const double* shift_sum = nullptr, int zero_in = 0, double omega = 1.0) {
+                        const double* shift_sum = nullptr, int zero_in = 0, double omega = 1.0,
+                        const RefineUpd* u = nullptr) {
     const int target = variant_target(v);
+    if constexpr (sizeof(T) == 4) {
+        if (u) {
+            switch ((v - 1) / 3) {
+                case 4: launch_sweep<T, 64, 4, 2, false, false, true>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, 1.0, *u); return;
+                case 5: launch_sweep<T, 64, 8, 2, false, false, true>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, 1.0, *u); return;
+                case 6: launch_sweep<T, 128, 8, 2, false, false, true>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, 1.0, *u); return;
+                default: launch_sweep<T, 64, 16, 2, false, false, true>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, 1.0, *u); return;
+            }
+        }
+    }
     switch ((v - 1) / 3) {
         case 0: launch_sweep<T, 64, 8, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega); break;
         case 1: launch_sweep<T, 128, 4, 1>(s, L, pin, pout, b, c0, target, shift_sum, zero_in, nullptr, omega); break;
@@ -661,9 +692,12 @@ static mg_status tune_level(mg_handle* h, const Lvl<T>& L, T* pin, T* pout, T* b
 // reference kernels for what is left (or for everything, on levels that use
 // them).  shift_sum (optional): the first fused pass subtracts shift_sum[0]/N
 // from the iterate as it reads it; returns false if there was no fused pass.
+// upd (optional): when the last pass is a fused one that can apply the
+// refinement update, it does, and *upd_done is set.
 template <class T>
 static bool smooth(mg_handle* h, Hier<T>& H, int l, int nsweep, int c0, T*& cur, T*& alt,
-                   const double* shift_sum = nullptr, bool zero_in = false) {
+                   const double* shift_sum = nullptr, bool zero_in = false, const RefineUpd* upd = nullptr,
+                   bool* upd_done = nullptr) {
     const Launcher s = launcher(h);
     const LevelDims& d = H.d[l];
     const int tile = alt ? h->tile[l] : -1;
@@ -680,12 +714,16 @@ static bool smooth(mg_handle* h, Hier<T>& H, int l, int nsweep, int c0, T*& cur,
     int rem = nsweep;
     if (tile > 0) {
         const int spp = sweeps_per_pass(tile);
+        const bool with_upd = upd && rem % spp == 0 && has_update_variant<T>(tile, h->o.omega);
         for (; rem >= spp; rem -= spp) {
             // algorithmic bytes: one sweep's worth per sweep done (less the
-            // iterate's read when it starts from zero)
-            Prof pf(h, cls, spp * full - (zero_in ? (double)d.ncell() * sizeof(T) : 0.0));
+            // iterate's read when it starts from zero; plus the FP64 iterate's
+            // read and write when the pass also applies the update)
+            const bool u = with_upd && rem == spp;
+            Prof pf(h, cls, spp * full - (zero_in ? (double)d.ncell() * sizeof(T) : 0.0) + (u ? 16.0 * d.ncell() : 0.0));
             fused_sweep<T>(s, tile, H.L[l], cur, alt, H.rhs[l], c0, shifted ? nullptr : shift_sum, zero_in ? 1 : 0,
-                           h->o.omega);
+                           h->o.omega, u ? upd : nullptr);
+            if (u) *upd_done = true;
             shifted = true;
             zero_in = false;
             std::swap(cur, alt);
@@ -706,9 +744,12 @@ static bool fused_first_sweep(const mg_handle* h) {
 // red_done: the level's iterate was last updated by a red half-sweep (the
 // previous cycle's post-smoothing on this level), so a fused pre-smoothing pass
 // may leave out its first (red) stage.
+//
+// upd (level 0 only, optional): the refinement update, applied by the last
+// post-smoothing pass where it can be (*upd_done set), else left to the caller.
 template <class T>
 static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nullptr, bool zero_init = false,
-                   bool red_done = false) {
+                   bool red_done = false, const RefineUpd* upd = nullptr, bool* upd_done = nullptr) {
     const Launcher s = launcher(h);
     const LevelDims& d = H.d[l];
     if (l == H.nlev - 1) {
@@ -760,7 +801,7 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
         const ColGrid G = zgrid(c.nx, d.ny, c.nz, false, &nbp, sizeof(T) == 4 ? 8192 : 2048);
         s.x(k_prolong_col<T>, nbp, CBX * CBY, H.e[l + 1], H.a[l + 1], c.nx, c.ny, c.nz, G, cur);
     }
-    smooth(h, H, l, h->o.nu2, 1, cur, alt);
+    smooth(h, H, l, h->o.nu2, 1, cur, alt, nullptr, false, upd, upd_done);
     if (cur != H.e[l]) {
         Prof pf(h, MG_K_OTHER, 2.0 * d.ncell() * sizeof(T));
         s.x(k_copy<T>, lin_grid(d.ncell()).x, 256, H.e[l], cur, d.ncell());
@@ -971,8 +1012,14 @@ mg_status launch_iteration_kernels(SolveState& S) {
         // e starts from zero; from the second inner cycle on, the previous cycle's
         // post-smoothing (nu2 >= 1 sweeps, black then red) has left the red cells
         // of level 0 exactly where the next pre-smoothing's red half-sweep would put them
-        for (int m = 0; m < h->o.inner_m; m++) vcycle(h, H32, 0, nullptr, m == 0, m > 0 && h->o.nu2 >= 1);
-        {
+        // the last cycle's final level-0 pass applies the update p <- (p - mean) + s e
+        // where its variant allows
+        const RefineUpd upd{S.p, h->scal + 8, h->scal + 5};
+        bool upd_done = false;
+        for (int m = 0; m < h->o.inner_m; m++)
+            vcycle(h, H32, 0, nullptr, m == 0, m > 0 && h->o.nu2 >= 1, m + 1 == h->o.inner_m ? &upd : nullptr,
+                   &upd_done);
+        if (!upd_done) {
             Prof pf(h, MG_K_REFINE, 20.0 * N);
             if ((d0.ncell() & 1) == 0 && ((uintptr_t)S.p & 15) == 0)
                 s.x(k_refine_update2, (unsigned)((d0.ncell() / 2 + 511) / 512), 512, S.p, (const float*)h->fe[0],

@@ -786,17 +786,24 @@ struct Vec2<double> {
 // pre-smoothing starts with): Gauss-Seidel on one colour given the other is
 // exact, so repeating it reproduces the stored values bit for bit.
 //
+// UPD (FP32 plain passes of the refined solve): as each plane of the iterate is
+// written in final form, the FP64 refinement update of the same cells is done
+// too, p64 = (p64 - upd_sum[0] / n_cells) + upd_s[0] * (double)e, the expression
+// of k_refine_update2 (so the update pass of the outer iteration is left out).
+//
 // With shift_sum non-null, every value of pin is first reduced by
 // shift_sum[0] / n_cells (the mean-zero projection of the previous iterate, done
 // on the fly instead of as a separate pass; same arithmetic as k_sub_mean).
 // With zero_in set, the iterate entering the pass is zero and pin is not read:
 // its loads go through a buffer resource of range 0, which returns 0 (a
 // coarse-grid correction's first smoothing pass; no separate fill).
-template <class T, int TX, int TY, int NSW, bool RES = false, bool SOR = false, bool SKIP = false>
+template <class T, int TX, int TY, int NSW, bool RES = false, bool SOR = false, bool SKIP = false,
+          bool UPD = false>
 __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES ? 2 : 0)))
     k_rb_sweep(Lvl<T> L, const T* __restrict__ pin, T* __restrict__ pout, const T* __restrict__ b, int c0, int kc,
                int tiles_x, int tiles_y, const double* __restrict__ shift_sum, double n_cells, int zero_in,
-               T* __restrict__ rc, T omega, Bt bt) {
+               T* __restrict__ rc, T omega, double* __restrict__ p64, const double* __restrict__ upd_s,
+               const double* __restrict__ upd_sum, Bt bt) {
     int bid_, nb_;
     uintptr_t off_;
     if (!bt_enter(bt, blockIdx.x, gridDim.x, bid_, nb_, off_)) return;
@@ -806,6 +813,10 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
     b = rb(b, off_);
     shift_sum = rb(shift_sum, off_);
     rc = rb(rc, off_);
+    p64 = rb(p64, off_);
+    upd_s = rb(upd_s, off_);
+    upd_sum = rb(upd_sum, off_);
+    static_assert(!UPD || (sizeof(T) == 4 && !RES), "the fused refinement update is for FP32 plain passes");
     using V = typename Vec2<T>::type;
     constexpr int R = 2 * NSW;                  // number of colour stages
     static_assert(!SKIP || (NSW == 2 && !SOR), "the first stage may be skipped in Gauss-Seidel two-sweep passes");
@@ -893,6 +904,8 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
     };
     const bool xu = ia + 2 < nx, yu = gj + 1 < ny;
     const uint32_t cb = inpair ? (uint32_t)(gj * nx + ia) * (uint32_t)sizeof(T) : 0u;
+    const uint32_t cb64 = inpair ? (uint32_t)(gj * nx + ia) * 8u : 0u;   // the pair in an FP64 plane
+    const double upd_c = UPD ? upd_sum[0] / n_cells : 0.0, upd_scale = UPD ? upd_s[0] : 0.0;
     // Offsets of the upper faces (those of the pair itself at a wall, where the
     // value is masked).  They pass through an empty asm so the compiler cannot
     // see that they may equal another load's address and fold the loads into a
@@ -997,6 +1010,8 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
             fetch_ring(t + 2, ring);                  // in flight during this step
             fetch_fb(t + 1, fq[A]);
             fzq[A] = fetch_fz(t + 2);
+            double2 pold{};   // UPD: the FP64 values of the pair on this step's output plane
+            if constexpr (UPD) pold = buf_ld2(buf_rsrc(p64 + (size_t)kclamp(t - R + 1) * plane), cb64, (const double*)nullptr);
             epilogue(t - R - 1, ac);
             const int e = (c0 + i0 + gj + t) & 1;
             const int dist = e ? dist1 : dist0;
@@ -1037,6 +1052,12 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
                         out.x = e ? vold : vnew;
                         out.y = e ? vnew : vold;
                         buf_st2(out, buf_rsrc(pout + (size_t)z * plane), cb);
+                        if constexpr (UPD) {
+                            double2 q;
+                            q.x = (pold.x - upd_c) + upd_scale * (double)out.x;
+                            q.y = (pold.y - upd_c) + upd_scale * (double)out.y;
+                            buf_st2(q, buf_rsrc(p64 + (size_t)z * plane), cb64);
+                        }
                     }
                 }
             });

@@ -172,7 +172,10 @@ def test_fused_sweep_tiles_bit_identical(precision, n):
     plane steps (the FP32 two-sweep pass runs two steps per iteration).  This also covers the
     zero-input first pass of each coarse correction (the reference fills instead)
     and, in FP32 for the tiles that have it, the pre-smoothing pass that forms and
-    restricts the residual itself (the reference restricts in a separate pass)."""
+    restricts the residual itself (the reference restricts in a separate pass), the
+    pre-smoothing pass that leaves out its red stage from the second inner cycle on,
+    and the two-sweep post-smoothing pass that applies the FP64 refinement update
+    (the reference updates in a separate pass)."""
     from paper_1410_8568_amd import mg
     P = ragged_problem(n, seed=5)
     ref_p, ref_st = gpu_solve(P, precision=precision, tol=1e-10, tile=-1)
