@@ -659,6 +659,9 @@ def main():
             tight["fp64_cycles"] = stt[-1]["cycles"]
             tight["speedup_fp32_refined_vs_fp64"] = mst / tight["fp32_refined_ms"]
             tight_host["fp64_tol_%g" % args.tight_tol] = p.cpu().numpy()
+            a32 = tight_host["fp32_refined_tol_%g" % args.tight_tol]
+            a64 = tight_host["fp64_tol_%g" % args.tight_tol]
+            tight["rel_l2_fp32_refined_vs_fp64"] = float(np.linalg.norm(a32 - a64) / np.linalg.norm(a64))
         S64.close()
         prof64 = profiled(lambda profile: build("fp64", profile), b, p, args.tol)
         rel = (torch.linalg.vector_norm(p32 - p64) / torch.linalg.vector_norm(p64)).item()
