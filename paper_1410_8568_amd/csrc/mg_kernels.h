@@ -82,6 +82,80 @@ __device__ __forceinline__ float quot(float num, float d) {
 }
 __device__ __forceinline__ double quot(double num, double d) { return num / d; }
 
+// ---------------------------------------------------------------- prolongation corner values
+//
+// Flux-conserving prolongation (eqs. 13-14, extended to the octant corners of a
+// 3-D cell): the fine child of coarse cell C on x side sx (C - 1 or C + 1), y
+// side sy and z side sz gets (1/8) * sum over the 8 corners T of its octant of
+// V_T = sum(a e) / sum(a) over the 2^|T| coarse cells that share corner T (T =
+// {} is C itself, V = e_C), a being the coarse cell weight.  A corner's cells
+// are summed with C first, then its x neighbour, y neighbour, x-y neighbour,
+// lower plane before upper; the corners in the order {}, x, y, xy, z, xz, yz,
+// xyz.  The products a e are formed with contraction off, so every kernel that
+// applies the prolongation through these helpers gets the same bits, whatever
+// its launch shape (a contracted product would be rounded differently in a
+// kernel's prologue and in its loop).
+
+// One coarse plane as seen from one fine x-pair: a and w = a e at columns
+// (I, I - 1, I + 1) of row J and of the y-side row Jy (walls: clamped), and e_C.
+template <class T>
+struct ProPlane {
+    T a0, am, ap, ay0, aym, ayp;
+    T w0, wm, wp, wy0, wym, wyp;
+    T e0;
+};
+template <class T>
+__device__ __forceinline__ ProPlane<T> pro_plane(T a0, T am, T ap, T ay0, T aym, T ayp, T e0, T em, T ep, T ey0,
+                                                 T eym, T eyp) {
+#pragma clang fp contract(off)
+    ProPlane<T> c;
+    c.a0 = a0; c.am = am; c.ap = ap; c.ay0 = ay0; c.aym = aym; c.ayp = ayp;
+    c.e0 = e0;
+    c.w0 = a0 * e0; c.wm = am * em; c.wp = ap * ep;
+    c.wy0 = ay0 * ey0; c.wym = aym * eym; c.wyp = ayp * eyp;
+    return c;
+}
+
+// Corners on the face between coarse planes lo (below) and up: z, yz and, per
+// child (0: x side I - 1, 1: I + 1), xz and xyz.
+template <class T>
+struct ProFace {
+    T z, yz, xz[2], xyz[2];
+};
+template <class T>
+__device__ __forceinline__ ProFace<T> pro_face(const ProPlane<T>& lo, const ProPlane<T>& up) {
+#pragma clang fp contract(off)
+    ProFace<T> f;
+    f.z = quot(lo.w0 + up.w0, lo.a0 + up.a0);
+    f.yz = quot(((lo.w0 + lo.wy0) + up.w0) + up.wy0, ((lo.a0 + lo.ay0) + up.a0) + up.ay0);
+#pragma unroll
+    for (int e = 0; e < 2; e++) {
+        const T lax = e ? lo.ap : lo.am, lwx = e ? lo.wp : lo.wm;
+        const T lay = e ? lo.ayp : lo.aym, lwy = e ? lo.wyp : lo.wym;
+        const T uax = e ? up.ap : up.am, uwx = e ? up.wp : up.wm;
+        const T uay = e ? up.ayp : up.aym, uwy = e ? up.wyp : up.wym;
+        f.xz[e] = quot(((lo.w0 + lwx) + up.w0) + uwx, ((lo.a0 + lax) + up.a0) + uax);
+        f.xyz[e] = quot(((((((lo.w0 + lwx) + lo.wy0) + lwy) + up.w0) + uwx) + up.wy0) + uwy,
+                        ((((((lo.a0 + lax) + lo.ay0) + lay) + up.a0) + uax) + up.ay0) + uay);
+    }
+    return f;
+}
+
+// Sum over the octant corners of child e of coarse plane c0 whose z corners are
+// those of face f (unscaled: the correction is 1/8 of it).
+template <class T>
+__device__ __forceinline__ T pro_child(const ProPlane<T>& c0, const ProFace<T>& f, int e) {
+#pragma clang fp contract(off)
+    const T vy = quot(c0.w0 + c0.wy0, c0.a0 + c0.ay0);
+    const T ax = e ? c0.ap : c0.am, wx = e ? c0.wp : c0.wm;
+    const T axy = e ? c0.ayp : c0.aym, wxy = e ? c0.wyp : c0.wym;
+    T t = c0.e0;
+    t += quot(c0.w0 + wx, c0.a0 + ax);
+    t += vy;
+    t += quot(((c0.w0 + wx) + c0.wy0) + wxy, ((c0.a0 + ax) + c0.ay0) + axy);
+    return (((t + f.z) + f.xz[e]) + f.yz) + f.xyz[e];
+}
+
 // Successive over-relaxation of a Gauss-Seidel value g (feature 5): the cell
 // moves omega times the Gauss-Seidel step from its current value c[oc].  The
 // reference kernel forms the same expression, so both agree bit for bit.
@@ -1592,20 +1666,14 @@ __global__ void __launch_bounds__(CBX* CBY) k_resid_restrict_cells(Lvl<T> L, con
     }
 }
 
-// Flux-conserving prolongation and correction, z-marching over coarse planes.
-// Thread (I, j) owns the fine cell pair i = 2I, 2I+1 of fine row j: both are
-// children of coarse column I with the same y side (Jy) and opposite x sides
-// (I-1 for the even child, I+1 for the odd one, clamped = wall mirror).  For
-// each child, corner T of its octant has V_T = sum a e / sum a over the 2^|T|
-// coarse cells sharing it (T = {} is the coarse cell itself, V = e_C); the
-// child gets (1/8) * sum_T V_T, the corners summed in the order {}, x, y, xy, z,
-// xz, yz, xyz and the cells of a corner with x fastest, then y, then z (lower
-// plane first).  Each step handles the two fine planes 2K, 2K+1 of coarse plane
-// K: the in-plane corners ({}, x, y, xy) are shared by both, the corners on the
-// face K-1/2 were computed in the previous step (as face K+1/2 of plane K-1),
-// and the corners y, z, yz are shared by the two children.  The coarse plane
-// K+1 and the fine planes of the next step are loaded one step ahead.  G.kc
-// counts coarse planes.
+// Flux-conserving prolongation and correction (pro_plane / pro_face /
+// pro_child), z-marching over coarse planes.  Thread (I, j) owns the fine cell
+// pair i = 2I, 2I+1 of fine row j: both are children of coarse column I with
+// the same y side (Jy) and opposite x sides (I-1 for the even child, I+1 for the
+// odd one, clamped = wall mirror).  Each step handles the two fine planes 2K,
+// 2K+1 of coarse plane K: the corners on the face K-1/2 were computed in the
+// previous step (as face K+1/2 of plane K-1).  The coarse plane K+1 and the fine
+// planes of the next step are loaded one step ahead.  G.kc counts coarse planes.
 template <class T>
 __global__ void __launch_bounds__(CBX* CBY) k_prolong_col(const T* __restrict__ ec, const T* __restrict__ ac,
                                                          int cnx, int cny, int cnz, ColGrid G, T* __restrict__ ef, Bt bt) {
@@ -1627,78 +1695,30 @@ __global__ void __launch_bounds__(CBX* CBY) k_prolong_col(const T* __restrict__ 
     const int Jy = (j & 1) ? min(J + 1, cny - 1) : max(J - 1, 0);
     const size_t cplane = (size_t)cnx * cny;
     const size_t rJ = (size_t)J * cnx, rY = (size_t)Jy * cnx;
-    // one coarse plane: (a, w = a*e) at columns (x0 = I, xm = Im, xp = Ip) x (J, Jy)
-    struct CP {
-        T a0, am, ap, ay0, aym, ayp;
-        T w0, wm, wp, wy0, wym, wyp;
-        T e0;
-    };
     auto load = [&](int K) {
-        CP c;
         const size_t base = (size_t)K * cplane;
-        c.a0 = ac[base + rJ + I]; c.am = ac[base + rJ + Im]; c.ap = ac[base + rJ + Ip];
-        c.ay0 = ac[base + rY + I]; c.aym = ac[base + rY + Im]; c.ayp = ac[base + rY + Ip];
-        c.e0 = ec[base + rJ + I];
-        c.w0 = c.a0 * c.e0;
-        c.wm = c.am * ec[base + rJ + Im];
-        c.wp = c.ap * ec[base + rJ + Ip];
-        c.wy0 = c.ay0 * ec[base + rY + I];
-        c.wym = c.aym * ec[base + rY + Im];
-        c.wyp = c.ayp * ec[base + rY + Ip];
-        return c;
-    };
-    // corners on the face between coarse planes lo (below) and up: z, yz and,
-    // per child, xz and xyz
-    struct Face {
-        T z, yz, xz[2], xyz[2];
-    };
-    auto face = [&](const CP& lo, const CP& up) {
-        Face f;
-        f.z = quot(lo.w0 + up.w0, lo.a0 + up.a0);
-        f.yz = quot(((lo.w0 + lo.wy0) + up.w0) + up.wy0, ((lo.a0 + lo.ay0) + up.a0) + up.ay0);
-#pragma unroll
-        for (int e = 0; e < 2; e++) {
-            const T lax = e ? lo.ap : lo.am, lwx = e ? lo.wp : lo.wm;
-            const T lay = e ? lo.ayp : lo.aym, lwy = e ? lo.wyp : lo.wym;
-            const T uax = e ? up.ap : up.am, uwx = e ? up.wp : up.wm;
-            const T uay = e ? up.ayp : up.aym, uwy = e ? up.wyp : up.wym;
-            f.xz[e] = quot(((lo.w0 + lwx) + up.w0) + uwx, ((lo.a0 + lax) + up.a0) + uax);
-            f.xyz[e] = quot(((((((lo.w0 + lwx) + lo.wy0) + lwy) + up.w0) + uwx) + up.wy0) + uwy,
-                            ((((((lo.a0 + lax) + lo.ay0) + lay) + up.a0) + uax) + up.ay0) + uay);
-        }
-        return f;
+        return pro_plane<T>(ac[base + rJ + I], ac[base + rJ + Im], ac[base + rJ + Ip], ac[base + rY + I],
+                            ac[base + rY + Im], ac[base + rY + Ip], ec[base + rJ + I], ec[base + rJ + Im],
+                            ec[base + rJ + Ip], ec[base + rY + I], ec[base + rY + Im], ec[base + rY + Ip]);
     };
     const size_t fplane = (size_t)nx * ny;
     const size_t fcol = (size_t)j * nx + 2 * I;
-    CP c0 = load(K0), cp = load(min(K0 + 1, cnz - 1));
-    Face fl = face(load(max(K0 - 1, 0)), c0);          // face K0 - 1/2 (wall: mirror)
+    ProPlane<T> c0 = load(K0), cp = load(min(K0 + 1, cnz - 1));
+    ProFace<T> fl = pro_face(load(max(K0 - 1, 0)), c0);   // face K0 - 1/2 (wall: mirror)
     V n0 = *reinterpret_cast<const V*>(ef + (size_t)(2 * K0) * fplane + fcol);
     V n1 = *reinterpret_cast<const V*>(ef + (size_t)(2 * K0 + 1) * fplane + fcol);
     for (int K = K0; K < K1; K++) {
         V f0 = n0, f1 = n1;
-        const CP cq = K + 1 < K1 ? load(min(K + 2, cnz - 1)) : cp;
+        const ProPlane<T> cq = K + 1 < K1 ? load(min(K + 2, cnz - 1)) : cp;
         if (K + 1 < K1) {
             n0 = *reinterpret_cast<const V*>(ef + (size_t)(2 * K + 2) * fplane + fcol);
             n1 = *reinterpret_cast<const V*>(ef + (size_t)(2 * K + 3) * fplane + fcol);
         }
-        const Face fu = face(c0, cp);                   // face K + 1/2 (wall: mirror)
-        const T vy = quot(c0.w0 + c0.wy0, c0.a0 + c0.ay0);
-        T t0[2], t1[2];
-#pragma unroll
-        for (int e = 0; e < 2; e++) {
-            const T ax = e ? c0.ap : c0.am, wx = e ? c0.wp : c0.wm;
-            const T axy = e ? c0.ayp : c0.aym, wxy = e ? c0.wyp : c0.wym;
-            T t = c0.e0;
-            t += quot(c0.w0 + wx, c0.a0 + ax);
-            t += vy;
-            t += quot(((c0.w0 + wx) + c0.wy0) + wxy, ((c0.a0 + ax) + c0.ay0) + axy);
-            t0[e] = (((t + fl.z) + fl.xz[e]) + fl.yz) + fl.xyz[e];
-            t1[e] = (((t + fu.z) + fu.xz[e]) + fu.yz) + fu.xyz[e];
-        }
-        f0.x += t0[0] * T(0.125);
-        f0.y += t0[1] * T(0.125);
-        f1.x += t1[0] * T(0.125);
-        f1.y += t1[1] * T(0.125);
+        const ProFace<T> fu = pro_face(c0, cp);   // face K + 1/2 (wall: mirror)
+        f0.x += pro_child(c0, fl, 0) * T(0.125);
+        f0.y += pro_child(c0, fl, 1) * T(0.125);
+        f1.x += pro_child(c0, fu, 0) * T(0.125);
+        f1.y += pro_child(c0, fu, 1) * T(0.125);
         *reinterpret_cast<V*>(ef + (size_t)(2 * K) * fplane + fcol) = f0;
         *reinterpret_cast<V*>(ef + (size_t)(2 * K + 1) * fplane + fcol) = f1;
         fl = fu;
