@@ -233,10 +233,13 @@ def write_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, n, gib=1):
     dispatch) are scaled by what they read for the plain copy of known size.  The
     kernel class is the FP32 fine-grid smoother: among the k_rb_sweep<float, ...>
     dispatches of the solves (from the first finest-level residual pass on; the
-    setup's tuning runs come before), every dispatch whose fetch is at least 40% of the
-    largest (the finest level; the next level moves 8x less), fused-restriction
-    and plain passes alike, as the bench's roofline averages over both.  Dispatches of the two runs are
-    paired by their order within each (kernel, grid) group.  n: the grid size of
+    setup's tuning runs come before), every dispatch whose fetch is at least 20% of the
+    largest (the finest level; the next level moves 8x less, and the finest
+    level's passes differ by up to 2.4x: a pass entering from zero reads no
+    iterate, the last one also updates the FP64 iterate), fused-restriction,
+    plain and update passes alike, as the bench's roofline averages over all.  The finest
+    level's dispatches of each kernel are picked in each run by its own counter and
+    paired by their order.  n: the grid size of
     the bench run the counters were taken on."""
     copy_bytes = gib * (1 << 30)
 
@@ -259,16 +262,23 @@ def write_traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, n, gib=1):
                 g.setdefault((r["Kernel_Name"].split("(")[0], r["Grid_Size"]), []).append(float(r["Counter_Value"]))
         return g
 
-    F, W = groups(fetch_dir), groups(write_dir)
-    top = max(max(v) for v in F.values())
+    def finest(g):
+        # the finest level's dispatches of each kernel, in order (the two runs may tune
+        # coarser levels differently, so the groups are filtered before pairing)
+        top = max(max(v) for v in g.values())
+        out = {}
+        for (name, _), v in sorted(g.items()):
+            out.setdefault(name, []).extend(x for x in v if x >= 0.2 * top)
+        return out
+
+    F, W = finest(groups(fetch_dir)), finest(groups(write_dir))
     fetch, write, kernels = [], [], set()
-    for k, fv in F.items():
-        wv = W.get(k, [])
-        for i, f in enumerate(fv):
-            if f >= 0.4 * top and i < len(wv):
-                fetch.append(f * 1024.0 * fs)
-                write.append(wv[i] * 1024.0 * ws)
-                kernels.add(k[0].replace("void mgk::", ""))
+    for name, fv in F.items():
+        wv = W.get(name, [])
+        for f, w in zip(fv, wv):
+            fetch.append(f * 1024.0 * fs)
+            write.append(w * 1024.0 * ws)
+            kernels.add(name.replace("void mgk::", ""))
     out = {"class": "smooth_fine", "n": n, "kernels": sorted(kernels), "dispatches": len(fetch),
            "fetch_bytes": sum(fetch) / len(fetch), "write_bytes": sum(write) / len(write),
            "bytes_per_launch": (sum(fetch) + sum(write)) / len(fetch), "fetch_scale": fs, "write_scale": ws,

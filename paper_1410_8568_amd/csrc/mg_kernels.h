@@ -1084,8 +1084,13 @@ __global__ void __launch_bounds__((TX / 2 + 2 * NSW) * (TY + 4 * NSW - 2 + (RES 
             fetch_ring(t + 2, ring);                  // in flight during this step
             fetch_fb(t + 1, fq[A]);
             fzq[A] = fetch_fz(t + 2);
-            double2 pold{};   // UPD: the FP64 values of the pair on this step's output plane
-            if constexpr (UPD) pold = buf_ld2(buf_rsrc(p64 + (size_t)kclamp(t - R + 1) * plane), cb64, (const double*)nullptr);
+            // UPD: the FP64 values of the pair on this step's output plane (tile pairs
+            // only; the ring's lanes write no output)
+            double2 pold{};
+            if constexpr (UPD) {
+                if (dist0 == 0 && dist1 == 0)
+                    pold = buf_ld2(buf_rsrc(p64 + (size_t)kclamp(t - R + 1) * plane), cb64, (const double*)nullptr);
+            }
             epilogue(t - R - 1, ac);
             const int e = (c0 + i0 + gj + t) & 1;
             const int dist = e ? dist1 : dist0;
