@@ -773,11 +773,14 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
     // pass is all of it), that pass also forms the residual and its restriction
     const int rtile = alt ? h->rtile[l] : 0;
     if (rtile > 0) {
-        const double sweep_bytes = 2.0 * (3.0 * d.ncell() + d.nfaces()) * sizeof(T) -
+        // a pass that leaves out its red stage is credited with the three
+        // half-sweeps it does (1.5 sweeps' algorithmic bytes)
+        const bool skip = sizeof(T) == 4 && red_done && !zero_init && h->o.omega == 1.0;
+        const double sweep_bytes = (skip ? 1.5 : 2.0) * (3.0 * d.ncell() + d.nfaces()) * sizeof(T) -
                                    (zero_init ? (double)d.ncell() * sizeof(T) : 0.0);
         Prof pf(h, l == 0 ? MG_K_SMOOTH_FINE : MG_K_SMOOTH, sweep_bytes + restrict_bytes);
         fused_sweep_restrict<T>(s, rtile, H.L[l], cur, alt, H.rhs[l], shift_sum, zero_init ? 1 : 0, H.rhs[l + 1],
-                                h->o.omega, red_done && !zero_init && h->o.omega == 1.0);
+                                h->o.omega, skip);
         std::swap(cur, alt);
     } else if (h->o.restrict64) {
         // residual stored in the (free) ping-pong buffer, then the 64-point restriction
