@@ -99,10 +99,10 @@ typedef struct {
                         b_bar - L p is recomputed every iteration, so history and tolerance mean
                         the same as for the V-cycle iteration; stats.cycles counts iterations (one
                         V-cycle each).  Needs 32 more bytes of workspace per cell. */
-    /* Paper-faithful cycle variants (the defaults give the standard cycle).  Any omega runs
-       through the fused passes (bit-identical to the reference kernels); restrict64 runs every
-       level's smoother with the one-colour-per-pass reference kernels (the fused passes restrict
-       with the 8-child mean only). */
+    /* Paper-faithful cycle variants (the defaults give the standard cycle).  Any omega, and
+       restrict64, run through the fused passes (bit-identical to the reference kernels); with
+       restrict64 the residual is restricted by a separate pass (the fused pre-smoothing passes
+       restrict with the 8-child mean only). */
     double omega;          /* SOR factor of the red-black smoother, 0 < omega < 2 (feature 5);
                               default 1 = Gauss-Seidel */
     int restrict64;        /* 1: 64-point restriction (transpose of trilinear interpolation, times 4)

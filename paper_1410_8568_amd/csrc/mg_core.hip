@@ -325,11 +325,6 @@ mg_status setup_launch(mg_handle* h, const double* bx, const double* by, const d
     const bool f32 = h->o.precision == MG_FP32_REFINED;
     for (int l = 0; l < MG_MAX_LEVELS; l++) h->tile[l] = h->rtile[l] = 0;
     for (int l = 0; l + 1 < L.nlev; l++) {
-        if (h->o.restrict64) {   // the fused passes restrict with the 8-child mean only
-            h->tile[l] = -1;
-            h->rtile[l] = 0;
-            continue;
-        }
         if (h->o.tile != 0) {
             h->tile[l] = h->o.tile;
             h->rtile[l] = (h->o.nu1 == 2 && (f32 ? has_restrict_variant<float>(h->o.tile)
@@ -352,6 +347,9 @@ mg_status setup_launch(mg_handle* h, const double* bx, const double* by, const d
         }
         if (r != MG_OK) return r;
     }
+    // the fused pre-smoothing passes restrict with the 8-child mean only
+    if (h->o.restrict64)
+        for (int l = 0; l < MG_MAX_LEVELS; l++) h->rtile[l] = 0;
     // validation flags land in the pinned host block; setup_finish reads them
     HIPCHK(hipMemcpyAsync(setup_flags(h), h->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     return MG_OK;
@@ -783,13 +781,15 @@ static void vcycle(mg_handle* h, Hier<T>& H, int l, const double* shift_sum = nu
                                 h->o.omega, skip);
         std::swap(cur, alt);
     } else if (h->o.restrict64) {
-        // residual stored in the (free) ping-pong buffer, then the 64-point restriction
+        // residual stored in whichever of the level's two iterate buffers the
+        // smoothing left free, then the 64-point restriction
         smooth(h, H, l, h->o.nu1, 0, cur, alt, shift_sum, zero_init);
+        T* res = cur == H.e[l] ? H.tmp[l] : H.e[l];
         Prof pf(h, MG_K_RESTRICT, restrict_bytes + 2.0 * d.ncell() * sizeof(T));
         int nbr = 0;
         const ColGrid G = zgrid(d.nx / 2, d.ny, d.nz, false, &nbr);
-        s.x(k_resid_cells<T, 2, 2>, nbr, CBX * CBY, H.L[l], cur, H.rhs[l], G, nullptr, nullptr, h->part, H.tmp[l]);
-        s.x(k_restrict64<T>, lin_grid(c.ncell()).x, 256, H.tmp[l], d.nx, d.ny, d.nz, H.rhs[l + 1]);
+        s.x(k_resid_cells<T, 2, 2>, nbr, CBX * CBY, H.L[l], cur, H.rhs[l], G, nullptr, nullptr, h->part, res);
+        s.x(k_restrict64<T>, lin_grid(c.ncell()).x, 256, (const T*)res, d.nx, d.ny, d.nz, H.rhs[l + 1]);
     } else {
         smooth(h, H, l, h->o.nu1, 0, cur, alt, shift_sum, zero_init);
         Prof pf(h, MG_K_RESTRICT, restrict_bytes);

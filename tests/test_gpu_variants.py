@@ -76,8 +76,23 @@ def test_variant_options_are_validated():
             mg.Solver(bx, by, bz, **kw)
         assert ei.value.status == mg.MG_E_INVALID, kw
     S = mg.Solver(bx, by, bz, restrict64=True)
-    assert S.tiles()[:-1] == [-1] * (len(S.levels()) - 1)
+    assert all(t == -1 or 1 <= t <= mg.MG_NUM_TILES for t in S.tiles()[:-1])
     S.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_restrict64_fused_tiles_bit_identical_to_reference(precision):
+    """With the 64-point restriction the smoother runs the fused passes too (the
+    residual goes to whichever iterate buffer the passes left free, one or two
+    sweeps per pass, ragged tiles and chunks): every tile gives exactly the
+    reference one-colour kernels' iterates."""
+    from paper_1410_8568_amd import mg
+    P = ragged_problem((64, 48, 40), seed=6)
+    ref_p, ref_st = gpu_solve(P, precision=precision, tol=1e-10, tile=-1, restrict64=True)
+    for tile in range(1, mg.MG_NUM_TILES + 1):
+        p, st = gpu_solve(P, precision=precision, tol=1e-10, tile=tile, restrict64=True)
+        assert st["history"] == ref_st["history"], tile
+        assert np.array_equal(p, ref_p), tile
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
