@@ -385,9 +385,9 @@ VARIANT_SET = [
 def variant_bench(args):
     """The paper-faithful cycle variants on the benchmark's drop-splash field:
     cycles, gamma and time to the tolerance for the FP64 and FP32-refined
-    solvers (a non-default smoother or restriction runs the reference
-    one-colour kernels, so its time is not comparable with the fused default;
-    cycles and gamma are).  One JSON line per variant, then a summary line."""
+    solvers (every variant runs the fused smoother passes; the 64-point
+    restriction adds a separate residual pass and its gather).  One JSON line
+    per variant, then a summary line."""
     import torch
     from paper_1410_8568_amd import inputs, mg
     P = inputs.config2(args.n)
