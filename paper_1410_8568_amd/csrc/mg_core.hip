@@ -850,12 +850,15 @@ static void build_hier(mg_handle* h, double* p, Hier<double>& H64, Hier<float>& 
 }
 
 // Residual pass over level 0 (FP64; MODE as k_resid_col): the cell-pair
-// kernel when nx is even.  Returns the number of partial-sum blocks.
+// kernel when nx is even.  Returns the number of partial-sum blocks.  The flat
+// kernel serves the modes that write the residual where it fits; the norm alone
+// (MODE 0) is faster marching columns (512^3: 0.91 against 0.99 ms).
 template <int MODE>
 static int launch_resid(const Launcher& s, const Lvl<double>& L, const double* p, const double* b,
                         const double* inv_s, float* r32, double* part, double* r64 = nullptr) {
     int nb = 0;
-    if (resid_flat_fits(LevelDims{L.nx, L.ny, L.nz}) && ((uintptr_t)p & 15) == 0 && ((uintptr_t)b & 15) == 0) {
+    if (MODE != 0 && resid_flat_fits(LevelDims{L.nx, L.ny, L.nz}) && ((uintptr_t)p & 15) == 0 &&
+        ((uintptr_t)b & 15) == 0) {
         const uint32_t units = (uint32_t)((size_t)L.nx * L.ny * L.nz / 2);
         nb = (int)((units + RES_FLAT_THREADS - 1) / RES_FLAT_THREADS);
         s.x(k_resid_flat<MODE>, nb, RES_FLAT_THREADS, L, p, b, units, inv_s, r32, part, r64);

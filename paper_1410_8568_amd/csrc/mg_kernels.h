@@ -1346,8 +1346,9 @@ __global__ void __launch_bounds__(CBX* CBY) k_resid_col(Lvl<T> L, const T* __res
 //
 // r = b - L p on the finest level (FP64), one thread per cell pair (nx even,
 // arrays 16-byte aligned), 512 threads per workgroup in plain dispatch order:
-// for this one-pass stencil that measured 11% faster than marching columns,
-// the neighbouring rows and planes coming from the caches.  A neighbour across
+// where it writes the residual this one-pass stencil measured faster than
+// marching columns, the neighbouring rows and planes coming from the caches
+// (the norm alone is faster in columns).  A neighbour across
 // a wall is read at the cell itself and multiplied by a zero face.  MODE as
 // k_resid_col (0: partial sums of r^2 and p; 1: also r32 = float(r * inv_s);
 // 2: also r64 = r); one pair of partial sums per workgroup.  The stencil is
