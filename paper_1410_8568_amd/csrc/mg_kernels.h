@@ -1913,9 +1913,11 @@ __global__ void __launch_bounds__(CBX* CBY) k_fcg_direction(Lvl<double> L, const
     const int k0 = chunk * G.kc, k1 = min(nz, k0 + G.kc);
     const double beta = scal[14];
     double a = 0;
-    if (NC * I < nx && j < ny && k0 < k1) {
+    const bool active = NC * I < nx && j < ny;
+    if (k0 < k1) {   // the same for the whole workgroup
         const size_t plane = (size_t)nx * ny;
-        const CellOff o = cell_offsets<NC>(I, j, nx, ny);
+        // threads outside the grid load at cell (0, 0) and keep nothing
+        const CellOff o = cell_offsets<NC>(active ? I : 0, active ? j : 0, nx, ny);
         double vb[NC];
         {
             const size_t cb = (size_t)max(k0 - 1, 0) * plane + o.c;
@@ -1924,14 +1926,17 @@ __global__ void __launch_bounds__(CBX* CBY) k_fcg_direction(Lvl<double> L, const
         }
         Cells1<double, NC> cur = load_comb<NC>(L, z, so, beta, o, k0);
         for (int k = k0; k < k1; k++) {
+            __syncthreads();   // the row wavefronts in step (as in k_resid_cells)
             const Cells1<double, NC> nxt = load_comb<NC>(L, z, so, beta, o, plane_above(k, nz));
             double r[NC];
             cells_residual(cur, vb, nxt, r);   // r = 0 - L s
 #pragma unroll
             for (int e = 0; e < NC; e++) {
                 const double qv = -r[e];
-                q[(size_t)k * plane + o.c + e] = qv;
-                a += cur.p[e] * qv;
+                if (active) {
+                    q[(size_t)k * plane + o.c + e] = qv;
+                    a += cur.p[e] * qv;
+                }
                 vb[e] = cur.p[e];
             }
             cur = nxt;
