@@ -147,6 +147,62 @@ def test_bench_traffic_figure_is_tied_to_workload_and_kernel_code(tmp_path, monk
     assert bench.traffic_for("smooth_fine", 256) is None
 
 
+def _counter_csv(d, rows):
+    import csv
+    d.mkdir(parents=True, exist_ok=True)
+    with open(d / "bench_counter_collection.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Value"])
+        for r in rows:
+            w.writerow(r)
+
+
+def test_bench_traffic_pairs_the_finest_level_of_each_run(tmp_path, monkeypatch):
+    """bench.py --traffic: the finest-level smoother dispatches are picked in each
+    counter run by its own counter before FETCH and WRITE are paired, so a run
+    whose coarser levels were tuned to another kernel (the two runs tune
+    separately) pairs the same finest-level launches; tuning dispatches before
+    the first residual pass are left out; the copy calibration scales KiB to
+    bytes (FETCH x2, WRITE x1 here)."""
+    import json
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    src = tmp_path / "k.h"
+    src.write_text("int f() { return 1; }\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", ["k.h"])
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
+    A = "void mgk::k_rb_sweep<float, 64, 16, 2, false, false, false, false>(args)"
+    B = "void mgk::k_rb_sweep<float, 64, 8, 2, false, false, false, false>(args)"
+    U = "void mgk::k_rb_sweep<float, 64, 16, 2, false, false, false, true>(args)"
+    R = "void mgk::k_resid_flat<1>(args)"
+    # FETCH run: a tuning dispatch, then per cycle level 0 on A (and U), level 1 on A
+    fetch = [(1, A, 100, 9.0e6), (2, R, 5, 1.0)]
+    write = [(1, B, 100, 9.0e6), (2, R, 5, 1.0)]
+    d = 3
+    for cyc in range(3):
+        lvl0 = U if cyc == 2 else A
+        fetch += [(d, lvl0, 100, 3.0e6 + cyc), (d + 1, A, 100, 4.0e5)]
+        write += [(d, lvl0, 100, 5.0e5 + cyc), (d + 1, B, 50, 6.0e4)]   # level 1 tuned to B here
+        d += 2
+    _counter_csv(tmp_path / "F", fetch)
+    _counter_csv(tmp_path / "W", write)
+    _counter_csv(tmp_path / "CF", [(1, "__amd_rocclr_copyBuffer(x)", 1, 524288.0)])
+    _counter_csv(tmp_path / "CW", [(1, "__amd_rocclr_copyBuffer(x)", 1, 1048576.0)])
+    bench.write_traffic(str(tmp_path / "F"), str(tmp_path / "W"), str(tmp_path / "CF"), str(tmp_path / "CW"), 512)
+    e = json.load(open(tmp_path / "traffic.json"))["entries"][0]
+    assert e["n"] == 512 and e["dispatches"] == 3
+    kib = 1024.0
+    fetch0 = [(3.0e6 + c) * kib * 2.0 for c in range(3)]
+    write0 = [(5.0e5 + c) * kib for c in range(3)]
+    assert abs(e["fetch_bytes"] - sum(fetch0) / 3) < 1.0
+    assert abs(e["write_bytes"] - sum(write0) / 3) < 1.0
+    assert abs(e["bytes_per_launch"] - (sum(fetch0) + sum(write0)) / 3) < 1.0
+    assert sorted(e["kernels"]) == sorted([A.split("(")[0].replace("void mgk::", ""),
+                                           U.split("(")[0].replace("void mgk::", "")])
+
+
 def test_static_solve_refuses_before_any_device_call():
     """mg_solve_static validates on the host first: null arrays, a bad bc, an
     unaligned p, and a grid whose workspace exceeds the static array (160^3 in
