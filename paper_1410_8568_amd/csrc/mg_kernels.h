@@ -1651,6 +1651,7 @@ __global__ void __launch_bounds__(CBX* CBY) k_resid_restrict_cells(Lvl<T> L, con
     }
     T acc[NQ] = {};
     for (int k = k0; k < k1; k++) {
+        if (!(k & 1)) __syncthreads();   // the row wavefronts in step every plane (odd planes below)
         if (active) {
             const Cells1<T, NC> nxt = load_cells1<T, NC>(L, p, b, o, plane_above(k, nz));
             T r[NC];
